@@ -1,0 +1,217 @@
+/*
+ * hp.h -- C ABI of the MI355X HP-model genotype-phenotype map library
+ * (libhpmap.so).
+ *
+ * The library computes, for every binary H/P sequence of a chain of N
+ * monomers in a given index range, the ground state over all compact
+ * structures of a lattice box, decides whether it is unique, and accumulates
+ * per-structure designability; it then derives single-point-mutation
+ * statistics and neutral-network components from the resulting map.
+ * Model: S. J. Owen, "Graphical processing unit accelerated enumeration and
+ * exploration of model genotype-phenotype maps for protein folding"
+ * (arXiv 2008.05612), Methods (Eq. 1, ground-state rule), Eq. 2 and the
+ * designability/robustness definitions around it.
+ *
+ * Conventions shared by every call
+ *   - Sequences: bit i of the 64-bit index s is monomer i; 1 = H, 0 = P.
+ *   - Energy: E(s,c) = -(number of H-H non-bonded lattice contacts of
+ *     conformation c), i.e. Eq. 1 with E_HH = -1 and E_HP = E_PP = 0.
+ *   - Structures: directed Hamiltonian paths of the X*Y*Z box ("compact
+ *     self-avoiding walks").  A conformation is an orbit of directed paths
+ *     under the box's isometry group; a class (the reported phenotype) is an
+ *     orbit under isometries and chain reversal.  Both chain directions are
+ *     scored, since E(s, reverse(c)) = E(reverse(s), c).
+ *   - Ids: conformation ids rank the canonical keys (lexicographically
+ *     smallest site sequence of the orbit, site = x + X*(y + Y*z)); class ids
+ *     rank class keys (the smaller key of the two chain directions).
+ *   - A sequence is designing iff exactly one conformation attains the
+ *     minimum energy; its phenotype is that conformation's class id.  Any
+ *     other sequence has the deleterious phenotype HP_NONE.
+ *   - Memory: pointers named d_* are device pointers owned by the caller;
+ *     the library never allocates or frees device memory.  Host pointers
+ *     are owned by the caller too, except hp_structs handles, which the
+ *     library allocates and hp_structs_free releases.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Device
+ *     work is enqueued asynchronously; results are valid once the caller has
+ *     synchronised that stream.
+ *   - Errors: every call returns hp_status.  Nothing calls exit() or throws.
+ *     hp_last_error() describes the last failure of the calling thread.
+ */
+#ifndef HP_H
+#define HP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HP_OK = 0,
+    HP_EINVAL = -1,       /* bad argument: NULL, range, size, dims */
+    HP_ENOMEM = -2,       /* host allocation failed */
+    HP_EDEVICE = -3,      /* a HIP call failed */
+    HP_ERANGE = -4,       /* problem too large for the id or index types */
+    HP_EUNSUPPORTED = -5  /* valid request this build does not handle */
+} hp_status;
+
+#define HP_NONE 0xFFFFu
+
+/* Energy-kernel forms (both give bit-identical results). */
+#define HP_FORM_POPCOUNT 0  /* contact bitmasks, AND + popcount per pair        */
+#define HP_FORM_GEMM_I8 1   /* E = -P.C as an int8 matrix product on MFMA cores */
+
+typedef struct hp_structs hp_structs;
+
+typedef struct {
+    int32_t X, Y, Z;      /* box dimensions */
+    int32_t N;            /* chain length = X*Y*Z */
+    uint32_t group_order; /* number of box isometries */
+    uint64_t n_walks;     /* directed Hamiltonian paths = group_order * n_conf */
+    uint32_t n_conf;      /* conformations scored per sequence */
+    uint32_t n_class;     /* phenotypes */
+    uint32_t n_selfrev;   /* classes holding a single (reversal-symmetric) conformation */
+    uint32_t nbp;         /* non-bonded contacts of every compact structure */
+    uint32_t K;           /* odd-separation pairs (i, j), j - i >= 3 */
+    uint32_t W;           /* 32-bit words per contact bitmask, ceil(K/32) */
+    uint32_t K_pad;       /* depth of the int8 product: K + 2 index rows, rounded up to 32 */
+} hp_info;
+
+/*
+ * hp_structures -- enumerate and symmetry-reduce the compact structures of
+ * an X*Y*Z box (Methods, "HP and MJ lattice models": the library of folds is
+ * the set of compact self-avoiding walks).  Use Z = 1 for a 2D box.
+ * Host-only work.  *out receives a new immutable handle, safe to share
+ * between threads; release it with hp_structs_free.
+ * Errors: HP_EINVAL for dims < 1, N < 2, or a box with no Hamiltonian path;
+ * HP_ERANGE if N > 36 or the class count does not fit below HP_NONE.
+ */
+hp_status hp_structures(int X, int Y, int Z, hp_structs **out);
+void hp_structs_free(hp_structs *s);
+hp_status hp_structs_info(const hp_structs *s, hp_info *info);
+
+/*
+ * hp_structs_export -- copy the handle's tables to host buffers (any may be
+ * NULL):  walks[n_conf*N] canonical site sequence of each conformation;
+ * conf_to_class[n_conf]; rev_conf[n_conf] conformation of the reversed
+ * chain; self_rev[n_class]; pairs[K*2] the (i, j) of each bitmask/row
+ * position k; contacts[n_conf*nbp*2] the (i, j) contact pairs of each
+ * conformation, i < j, ascending.
+ */
+hp_status hp_structs_export(const hp_structs *s, uint8_t *walks, uint16_t *conf_to_class,
+                            uint32_t *rev_conf, uint8_t *self_rev, uint8_t *pairs,
+                            uint8_t *contacts);
+
+/*
+ * Device workspace holding the packed structure tables both kernel forms
+ * read (contact bitmasks, the int8 contact matrix in MFMA operand order,
+ * the pair table and conformation-to-class map).  hp_workspace_bytes gives
+ * its size; hp_upload fills caller memory d_ws (>= that many bytes, 256-byte
+ * aligned) asynchronously on `stream`.  The host source stays owned by the
+ * handle, so the handle must outlive the copy (synchronise before freeing).
+ */
+size_t hp_workspace_bytes(const hp_structs *s);
+hp_status hp_upload(const hp_structs *s, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * hp_enumerate -- ground states of every sequence s in [seq_lo, seq_hi)
+ * (Methods: minimum of Eq. 1 over all folds; a sequence with no unique
+ * minimum does not fold).  seq_hi <= 2^N.
+ *   d_out[s - seq_lo]   phenotype (class id) or HP_NONE; may be NULL.
+ *   d_emin[s - seq_lo]  minimum energy (int32, <= 0); may be NULL.
+ *   d_designability[q] += number of sequences in range with phenotype q
+ *                         (n_class uint64 counters; may be NULL).
+ *   d_nondesign[0]     += number of deleterious sequences (may be NULL).
+ * `form` selects HP_FORM_POPCOUNT or HP_FORM_GEMM_I8.  d_ws must hold the
+ * uploaded workspace of the same handle.
+ * Errors: HP_EINVAL (NULL handle/workspace, empty or out-of-range seq range,
+ * unknown form), HP_EDEVICE (launch failure).
+ */
+hp_status hp_enumerate(const hp_structs *s, const void *d_ws, int form, uint64_t seq_lo,
+                       uint64_t seq_hi, uint16_t *d_out, int32_t *d_emin,
+                       uint64_t *d_designability, uint64_t *d_nondesign, void *stream);
+
+/*
+ * Batched launch: several enumeration jobs, possibly of different lattices
+ * and uneven sizes, processed by ONE persistent kernel launch that takes
+ * fixed-size sequence tiles from a shared work list.  Each job has the
+ * meaning of one hp_enumerate call.  d_batch_ws is caller device memory of
+ * hp_batch_workspace_bytes(njobs) bytes holding the work list and its
+ * counter (both rewritten by every call).  The descriptor upload is a
+ * synchronous host-to-device copy made before the launch is enqueued.
+ * Errors: as hp_enumerate, for any job; HP_EINVAL if njobs < 1 or the
+ * workspace is too small.
+ */
+typedef struct {
+    const hp_structs *structs;
+    const void *d_ws;
+    uint64_t seq_lo, seq_hi;
+    uint16_t *d_out;
+    int32_t *d_emin;
+    uint64_t *d_designability;
+    uint64_t *d_nondesign;
+} hp_job;
+
+size_t hp_batch_workspace_bytes(int njobs);
+hp_status hp_enumerate_batch(const hp_job *jobs, int njobs, int form, void *d_batch_ws,
+                             size_t batch_ws_bytes, void *stream);
+
+/*
+ * Captured launches: hp_graph_capture_batch records the device work of
+ * hp_enumerate_batch (counter reset and persistent kernel, no memsets) into
+ * a hipGraph once; hp_graph_launch replays it on `stream`.  The work list is
+ * uploaded at capture time and must stay in d_batch_ws while the graph is
+ * used.  Designability counters accumulate on every replay.
+ */
+typedef struct hp_graph hp_graph;
+hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *d_batch_ws,
+                                 size_t batch_ws_bytes, hp_graph **out);
+hp_status hp_graph_launch(hp_graph *g, void *stream);
+void hp_graph_free(hp_graph *g);
+
+/*
+ * hp_neighbors -- single-point-mutation statistics of a complete map
+ * (Eq. 2: phi_pq; robustness rho_q = phi_qq; phi_del).  d_map holds the
+ * phenotype of all 2^N sequences.  For every designing genotype g with
+ * phenotype q and each of its N one-bit mutants p:
+ *   d_neutral[q] += (p == q);  d_deleterious[q] += (p == HP_NONE);
+ *   d_other[q]   += otherwise.
+ * The ratios of Eq. 2 are these counts divided by N * N_q.  If phi_q >= 0,
+ * d_phi_row[p] (p < n_class) and d_phi_row[n_class] (deleterious) += the
+ * mutants of phi_q-genotypes, i.e. the numerators of phi_{p,phi_q}.
+ * Counters are uint64 arrays of n_class (n_class + 1 for the row); any may
+ * be NULL.  Errors: HP_EINVAL for NULL map or phi_q >= n_class.
+ */
+hp_status hp_neighbors(const hp_structs *s, const uint16_t *d_map, uint64_t *d_neutral,
+                       uint64_t *d_deleterious, uint64_t *d_other, int32_t phi_q,
+                       uint64_t *d_phi_row, void *stream);
+
+/*
+ * hp_components -- neutral networks: connected components of the subgraph
+ * of the N-cube of sequences (edges = single point mutations) induced on
+ * genotypes of equal designing phenotype (Introduction, "spaghetti vs plum
+ * pudding"; the text on neutral networks in the results).
+ *   d_labels[g]   smallest genotype of g's component, 0xFFFFFFFF if g is
+ *                 deleterious (2^N entries, overwritten);
+ *   d_compsize[g] size of the component whose smallest genotype is g, 0 for
+ *                 every other g (2^N entries, overwritten);
+ *   d_ncomp[q]    number of components of phenotype q (n_class, overwritten);
+ *   d_largest[q]  size of q's largest component (n_class, overwritten).
+ * d_ncomp and d_largest may be NULL.  Requires N <= 31.
+ * Errors: HP_EINVAL for NULL labels/compsize/map; HP_ERANGE for N > 31.
+ */
+hp_status hp_components(const hp_structs *s, const uint16_t *d_map, uint32_t *d_labels,
+                        uint32_t *d_compsize, uint32_t *d_ncomp, uint32_t *d_largest,
+                        void *stream);
+
+/* Thread-local text of the last failure ("" if none). */
+const char *hp_last_error(void);
+
+/* Library version string. */
+const char *hp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HP_H */

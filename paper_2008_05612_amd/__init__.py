@@ -1,0 +1,27 @@
+"""MI355X-native HP-model genotype-phenotype map (arXiv 2008.05612 hot path).
+
+Thin Python binding over the C ABI of ``libhpmap.so`` (declared in
+``include/hp.h``).  Every step of the computation runs in the library's HIP
+kernels; this module only marshals arguments.  PyTorch supplies device memory
+and streams.  If the library is not built, importing works but every call
+raises ``LibraryMissing`` -- there is no fallback path.
+"""
+from ._binding import (  # noqa: F401
+    FORM_GEMM_I8,
+    FORM_POPCOUNT,
+    NONE,
+    HPError,
+    Job,
+    LibraryMissing,
+    Structures,
+    hp_components,
+    hp_enumerate,
+    hp_enumerate_batch,
+    hp_graph_capture_batch,
+    hp_neighbors,
+    hp_structures,
+    hp_upload,
+    hp_workspace_bytes,
+    library,
+    library_path,
+)

@@ -1,0 +1,391 @@
+// C ABI of libhpmap: argument checking, error reporting, workspace upload,
+// the sequence block loop, batched launches and their hipGraph capture.
+// Every entry point returns hp_status; no call exits or throws across the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hp_internal.h"
+#include "kernels.h"
+
+namespace hpmap {
+
+namespace {
+thread_local std::string g_last_error;
+
+// Sequences per kernel launch of hp_enumerate; longer ranges are streamed as
+// a loop of such blocks (the full 6x6 map is 64 blocks).
+constexpr uint64_t kBlockSeqs = uint64_t(1) << 30;
+
+hp_status device_fail(hipError_t e, const char *what)
+{
+    return fail(HP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+EnumJob make_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64_t hi, uint16_t *out,
+                 int32_t *emin, uint64_t *desig, uint64_t *nondesign)
+{
+    const char *base = static_cast<const char *>(d_ws);
+    EnumJob j{};
+    j.c2q = reinterpret_cast<const uint16_t *>(base + s->ws.c2q);
+    j.pairs = reinterpret_cast<const uint8_t *>(base + s->ws.pairs);
+    j.masks = reinterpret_cast<const uint32_t *>(base + s->ws.masks);
+    j.gemm_a = reinterpret_cast<const int8_t *>(base + s->ws.gemm_a);
+    j.out = out;
+    j.emin = emin;
+    j.desig = reinterpret_cast<unsigned long long *>(desig);
+    j.nondesign = reinterpret_cast<unsigned long long *>(nondesign);
+    j.lo = lo;
+    j.hi = hi;
+    j.N = s->N;
+    j.K = int32_t(s->K);
+    j.W = int32_t(s->W);
+    j.KB = int32_t(s->K_pad / 32);
+    j.n_conf = int32_t(s->n_conf);
+    j.n_tiles = int32_t((s->n_conf + kTileConf - 1) / kTileConf);
+    return j;
+}
+
+hp_status check_range(const hp_structs *s, const void *d_ws, uint64_t lo, uint64_t hi)
+{
+    if (!s)
+        return fail(HP_EINVAL, "structures handle is NULL");
+    if (!d_ws)
+        return fail(HP_EINVAL, "workspace pointer is NULL");
+    const uint64_t space = uint64_t(1) << s->N;
+    if (lo >= hi)
+        return fail(HP_EINVAL, "empty sequence range (seq_lo >= seq_hi)");
+    if (hi > space)
+        return fail(HP_EINVAL, "seq_hi exceeds 2^N");
+    return HP_OK;
+}
+
+struct BatchPlan {
+    std::vector<char> host;   // header + jobs + item starts
+    int kb_max = 0;
+    int n_items = 0;
+};
+
+hp_status plan_batch(const hp_job *jobs, int njobs, size_t ws_bytes, BatchPlan *plan)
+{
+    if (!jobs || njobs < 1)
+        return fail(HP_EINVAL, "batch needs at least one job");
+    if (ws_bytes < hp_batch_workspace_bytes(njobs))
+        return fail(HP_EINVAL, "batch workspace too small");
+    int kb_max = 1;
+    for (int i = 0; i < njobs; ++i) {
+        hp_status st = check_range(jobs[i].structs, jobs[i].d_ws, jobs[i].seq_lo, jobs[i].seq_hi);
+        if (st != HP_OK)
+            return st;
+        kb_max = std::max(kb_max, int(jobs[i].structs->K_pad / 32));
+    }
+    const GemmShape sh = kb_max <= 5 ? GemmShape{4, 4} : GemmShape{2, 4};
+    const uint64_t per = gemm_seqs_per_item(sh);
+    std::vector<int64_t> start(njobs + 1, 0);
+    for (int i = 0; i < njobs; ++i) {
+        const uint64_t n = jobs[i].seq_hi - jobs[i].seq_lo;
+        start[i + 1] = start[i] + int64_t((n + per - 1) / per);
+    }
+    if (start[njobs] > INT32_MAX)
+        return fail(HP_ERANGE, "batch has too many work items");
+    plan->host.assign(hp_batch_workspace_bytes(njobs), 0);
+    BatchHeader hdr{};
+    hdr.counter = 0;
+    hdr.njobs = njobs;
+    hdr.n_items = int32_t(start[njobs]);
+    hdr.kb_max = kb_max;
+    std::memcpy(plan->host.data(), &hdr, sizeof(hdr));
+    EnumJob *ej = reinterpret_cast<EnumJob *>(plan->host.data() + sizeof(BatchHeader));
+    for (int i = 0; i < njobs; ++i)
+        ej[i] = make_job(jobs[i].structs, jobs[i].d_ws, jobs[i].seq_lo, jobs[i].seq_hi,
+                         jobs[i].d_out, jobs[i].d_emin, jobs[i].d_designability,
+                         jobs[i].d_nondesign);
+    std::memcpy(plan->host.data() + sizeof(BatchHeader) + sizeof(EnumJob) * njobs, start.data(),
+                sizeof(int64_t) * (njobs + 1));
+    plan->kb_max = kb_max;
+    plan->n_items = hdr.n_items;
+    return HP_OK;
+}
+
+}  // namespace
+
+hp_status fail(hp_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+}  // namespace hpmap
+
+struct hp_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+using namespace hpmap;
+
+extern "C" {
+
+const char *hp_last_error(void) { return g_last_error.c_str(); }
+
+const char *hp_version(void) { return "hpmap 0.1 (gfx950)"; }
+
+hp_status hp_structures(int X, int Y, int Z, hp_structs **out)
+{
+    if (!out)
+        return fail(HP_EINVAL, "out pointer is NULL");
+    *out = nullptr;
+    hp_structs *s = new (std::nothrow) hp_structs();
+    if (!s)
+        return fail(HP_ENOMEM, "out of host memory");
+    std::string msg;
+    hp_status st;
+    try {
+        st = build_structures(X, Y, Z, s, &msg);
+    } catch (const std::bad_alloc &) {
+        st = HP_ENOMEM;
+        msg = "out of host memory";
+    }
+    if (st != HP_OK) {
+        delete s;
+        return fail(st, msg);
+    }
+    *out = s;
+    return HP_OK;
+}
+
+void hp_structs_free(hp_structs *s) { delete s; }
+
+hp_status hp_structs_info(const hp_structs *s, hp_info *info)
+{
+    if (!s || !info)
+        return fail(HP_EINVAL, "NULL argument");
+    info->X = s->X;
+    info->Y = s->Y;
+    info->Z = s->Z;
+    info->N = s->N;
+    info->group_order = s->G;
+    info->n_walks = s->n_walks;
+    info->n_conf = s->n_conf;
+    info->n_class = s->n_class;
+    info->n_selfrev = s->n_selfrev;
+    info->nbp = s->nbp;
+    info->K = s->K;
+    info->W = s->W;
+    info->K_pad = s->K_pad;
+    return HP_OK;
+}
+
+hp_status hp_structs_export(const hp_structs *s, uint8_t *walks, uint16_t *conf_to_class,
+                            uint32_t *rev_conf, uint8_t *self_rev, uint8_t *pairs,
+                            uint8_t *contacts)
+{
+    if (!s)
+        return fail(HP_EINVAL, "structures handle is NULL");
+    if (walks)
+        std::memcpy(walks, s->walks.data(), s->walks.size());
+    if (conf_to_class)
+        std::memcpy(conf_to_class, s->c2q.data(), s->c2q.size() * 2);
+    if (rev_conf)
+        std::memcpy(rev_conf, s->rev_conf.data(), s->rev_conf.size() * 4);
+    if (self_rev)
+        std::memcpy(self_rev, s->self_rev.data(), s->self_rev.size());
+    if (pairs)
+        std::memcpy(pairs, s->pairs.data(), s->pairs.size());
+    if (contacts)
+        std::memcpy(contacts, s->contacts.data(), s->contacts.size());
+    return HP_OK;
+}
+
+size_t hp_workspace_bytes(const hp_structs *s) { return s ? s->ws.total : 0; }
+
+hp_status hp_upload(const hp_structs *s, void *d_ws, size_t ws_bytes, void *stream)
+{
+    if (!s || !d_ws)
+        return fail(HP_EINVAL, "NULL argument");
+    if (ws_bytes < s->ws.total)
+        return fail(HP_EINVAL, "workspace smaller than hp_workspace_bytes()");
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0)
+        return fail(HP_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(d_ws);
+    struct Part { size_t off; const void *src; size_t bytes; } parts[] = {
+        {s->ws.c2q, s->c2q.data(), s->c2q.size() * 2},
+        {s->ws.pairs, s->pair_rows.data(), s->pair_rows.size()},
+        {s->ws.masks, s->masks.data(), s->masks.size() * 4},
+        {s->ws.gemm_a, s->gemm_a.data(), s->gemm_a.size()},
+    };
+    for (const Part &p : parts) {
+        if (!p.bytes)
+            continue;
+        hipError_t e = hipMemcpyAsync(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess)
+            return device_fail(e, "hp_upload");
+    }
+    return HP_OK;
+}
+
+hp_status hp_enumerate(const hp_structs *s, const void *d_ws, int form, uint64_t seq_lo,
+                       uint64_t seq_hi, uint16_t *d_out, int32_t *d_emin,
+                       uint64_t *d_designability, uint64_t *d_nondesign, void *stream)
+{
+    hp_status st = check_range(s, d_ws, seq_lo, seq_hi);
+    if (st != HP_OK)
+        return st;
+    if (form != HP_FORM_POPCOUNT && form != HP_FORM_GEMM_I8)
+        return fail(HP_EINVAL, "unknown kernel form");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const GemmShape shape = default_gemm_shape(int(s->K_pad / 32));
+    for (uint64_t lo = seq_lo; lo < seq_hi; lo += kBlockSeqs) {
+        const uint64_t hi = std::min(seq_hi, lo + kBlockSeqs);
+        EnumJob j = make_job(s, d_ws, lo, hi, d_out ? d_out + (lo - seq_lo) : nullptr,
+                             d_emin ? d_emin + (lo - seq_lo) : nullptr, d_designability,
+                             d_nondesign);
+        hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs) : launch_gemm(j, shape, hs);
+        if (e != hipSuccess)
+            return device_fail(e, "hp_enumerate launch");
+    }
+    return HP_OK;
+}
+
+size_t hp_batch_workspace_bytes(int njobs)
+{
+    if (njobs < 1)
+        return 0;
+    size_t b = sizeof(BatchHeader) + sizeof(EnumJob) * size_t(njobs) +
+               sizeof(int64_t) * size_t(njobs + 1);
+    return (b + 255) & ~size_t(255);
+}
+
+hp_status hp_enumerate_batch(const hp_job *jobs, int njobs, int form, void *d_batch_ws,
+                             size_t batch_ws_bytes, void *stream)
+{
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (form == HP_FORM_POPCOUNT) {
+        for (int i = 0; i < njobs && jobs; ++i) {
+            hp_status st = hp_enumerate(jobs[i].structs, jobs[i].d_ws, form, jobs[i].seq_lo,
+                                        jobs[i].seq_hi, jobs[i].d_out, jobs[i].d_emin,
+                                        jobs[i].d_designability, jobs[i].d_nondesign, stream);
+            if (st != HP_OK)
+                return st;
+        }
+        return (jobs && njobs >= 1) ? HP_OK : fail(HP_EINVAL, "batch needs at least one job");
+    }
+    if (form != HP_FORM_GEMM_I8)
+        return fail(HP_EINVAL, "unknown kernel form");
+    if (!d_batch_ws)
+        return fail(HP_EINVAL, "batch workspace is NULL");
+    BatchPlan plan;
+    hp_status st = plan_batch(jobs, njobs, batch_ws_bytes, &plan);
+    if (st != HP_OK)
+        return st;
+    // synchronous upload: the host plan is released on return
+    hipError_t e = hipMemcpy(d_batch_ws, plan.host.data(), plan.host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return device_fail(e, "batch upload");
+    e = launch_gemm_batch(d_batch_ws, plan.kb_max, plan.n_items, hs);
+    if (e != hipSuccess)
+        return device_fail(e, "batch launch");
+    return HP_OK;
+}
+
+hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *d_batch_ws,
+                                 size_t batch_ws_bytes, hp_graph **out)
+{
+    if (!out)
+        return fail(HP_EINVAL, "out pointer is NULL");
+    *out = nullptr;
+    if (form != HP_FORM_GEMM_I8)
+        return fail(HP_EUNSUPPORTED, "graph capture is provided for the int8 form");
+    if (!d_batch_ws)
+        return fail(HP_EINVAL, "batch workspace is NULL");
+    BatchPlan plan;
+    hp_status st = plan_batch(jobs, njobs, batch_ws_bytes, &plan);
+    if (st != HP_OK)
+        return st;
+    hipError_t e = hipMemcpy(d_batch_ws, plan.host.data(), plan.host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return device_fail(e, "batch upload");
+    hipStream_t cap = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess)
+        return device_fail(e, "capture stream");
+    hp_graph *g = new (std::nothrow) hp_graph();
+    if (!g) {
+        hipStreamDestroy(cap);
+        return fail(HP_ENOMEM, "out of host memory");
+    }
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_gemm_batch(d_batch_ws, plan.kb_max, plan.n_items, cap);
+        e = hipStreamEndCapture(cap, &g->graph);
+        if (le != hipSuccess)
+            e = le;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        hp_graph_free(g);
+        return device_fail(e, "graph capture");
+    }
+    *out = g;
+    return HP_OK;
+}
+
+hp_status hp_graph_launch(hp_graph *g, void *stream)
+{
+    if (!g || !g->exec)
+        return fail(HP_EINVAL, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HP_OK : device_fail(e, "graph launch");
+}
+
+void hp_graph_free(hp_graph *g)
+{
+    if (!g)
+        return;
+    if (g->exec)
+        hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        hipGraphDestroy(g->graph);
+    delete g;
+}
+
+hp_status hp_neighbors(const hp_structs *s, const uint16_t *d_map, uint64_t *d_neutral,
+                       uint64_t *d_deleterious, uint64_t *d_other, int32_t phi_q,
+                       uint64_t *d_phi_row, void *stream)
+{
+    if (!s || !d_map)
+        return fail(HP_EINVAL, "NULL structures or map");
+    if (phi_q >= int32_t(s->n_class))
+        return fail(HP_EINVAL, "phi_q >= n_class");
+    if (phi_q >= 0 && !d_phi_row)
+        return fail(HP_EINVAL, "phi_q given without a phi row buffer");
+    hipError_t e = launch_neighbors(d_map, s->N, int(s->n_class),
+                                    reinterpret_cast<unsigned long long *>(d_neutral),
+                                    reinterpret_cast<unsigned long long *>(d_deleterious),
+                                    reinterpret_cast<unsigned long long *>(d_other), phi_q,
+                                    phi_q >= 0 ? reinterpret_cast<unsigned long long *>(d_phi_row)
+                                               : nullptr,
+                                    static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HP_OK : device_fail(e, "hp_neighbors launch");
+}
+
+hp_status hp_components(const hp_structs *s, const uint16_t *d_map, uint32_t *d_labels,
+                        uint32_t *d_compsize, uint32_t *d_ncomp, uint32_t *d_largest,
+                        void *stream)
+{
+    if (!s || !d_map || !d_labels || !d_compsize)
+        return fail(HP_EINVAL, "NULL structures, map, labels or compsize");
+    if (s->N > 31)
+        return fail(HP_ERANGE, "components need N <= 31 (32-bit labels)");
+    hipError_t e = launch_components(d_map, s->N, d_labels, d_compsize, d_ncomp, d_largest,
+                                     int(s->n_class), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HP_OK : device_fail(e, "hp_components launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// Internal definitions shared by the host structure code, the C ABI and the
+// kernel launchers of libhpmap.  Not installed; the public surface is hp.h.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hp.h"
+
+namespace hpmap {
+
+constexpr int kMaxN = 36;            // sequences are 64-bit, ids 16-bit
+constexpr int kTileConf = 32;        // conformations per MFMA tile (rows of A)
+constexpr int kWindowConf = 16384;   // conformations per key window of the int8 form
+constexpr int kWindowTiles = kWindowConf / kTileConf;
+constexpr int kKeyConfBits = 17;     // global key = (n_HH << 17) | conformation id
+constexpr uint32_t kMaxConf = 1u << kKeyConfBits;
+
+// Byte offsets of the packed tables inside the device workspace.
+struct WsLayout {
+    size_t c2q = 0;      // uint16_t[n_conf]
+    size_t pairs = 0;    // uint8_t[K_pad][2]
+    size_t masks = 0;    // uint32_t[n_conf][W]
+    size_t gemm_a = 0;   // int8_t[n_tiles][K_pad/32][64 lanes][16]
+    size_t total = 0;
+};
+
+}  // namespace hpmap
+
+struct hp_structs {
+    int X = 0, Y = 0, Z = 0, N = 0;
+    uint32_t G = 0;
+    uint64_t n_walks = 0;
+    uint32_t n_conf = 0, n_class = 0, n_selfrev = 0, nbp = 0, K = 0, W = 0, K_pad = 0;
+    std::vector<uint8_t> walks;       // n_conf * N canonical site sequences, ascending
+    std::vector<uint16_t> c2q;        // conformation -> class
+    std::vector<uint32_t> rev_conf;   // conformation of the reversed chain
+    std::vector<uint8_t> self_rev;    // per class
+    std::vector<uint8_t> pairs;       // K * 2: (i, j) of bit / row k
+    std::vector<uint8_t> contacts;    // n_conf * nbp * 2, (i, j) ascending
+    std::vector<uint32_t> masks;      // n_conf * W contact bitmasks
+    std::vector<int8_t> gemm_a;       // int8 contact matrix in MFMA A-operand order
+    std::vector<uint8_t> pair_rows;   // K_pad * 2 (rows >= K are 0xFF markers)
+    hpmap::WsLayout ws;
+};
+
+namespace hpmap {
+
+// Host enumeration (structures.cpp).  Returns HP_OK or an error with msg set.
+hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg);
+
+// Error plumbing (capi.cpp).
+hp_status fail(hp_status st, const std::string &msg);
+
+}  // namespace hpmap

@@ -1,0 +1,422 @@
+// Host side of hp_structures: compact-structure enumeration, symmetry
+// reduction and packing of the tables the GPU kernels read.
+//
+// The structures of the model are the compact self-avoiding walks of a lattice
+// box (Methods, "HP and MJ lattice models"), i.e. its directed Hamiltonian
+// paths.  Each conformation (orbit under the box isometries) is produced once,
+// as its lexicographically smallest member: the depth-first search keeps, for
+// the current prefix, the set of isometries whose image of the prefix still
+// equals the prefix, and abandons the prefix as soon as one image becomes
+// smaller.  Because the search visits sites in ascending order, the surviving
+// walks come out already sorted, so conformation ids are emission ranks.
+//
+// Pruning of prefixes that cannot be completed, both exact necessary
+// conditions: (a) the unvisited sites plus the head are connected; (b) colour
+// balance of the bipartite lattice.  Sets are 64-bit site masks.
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cstring>
+#include <thread>
+
+#include "hp_internal.h"
+
+namespace hpmap {
+namespace {
+
+using Perm = std::array<uint8_t, kMaxN>;
+
+struct Box {
+    int X, Y, Z, N;
+    uint64_t full;
+    uint64_t nbr[kMaxN];
+    uint64_t colour_even;              // sites with x+y+z even
+    uint64_t lo_x, hi_x, lo_y, hi_y, lo_z, hi_z;  // sites that may shift in each direction
+    std::vector<Perm> group;
+};
+
+uint64_t bit(int s) { return uint64_t(1) << s; }
+
+uint64_t dilate(const Box &b, uint64_t m)
+{
+    const int XY = b.X * b.Y;
+    return ((m & b.hi_x) << 1) | ((m & b.lo_x) >> 1) | ((m & b.hi_y) << b.X) |
+           ((m & b.lo_y) >> b.X) | ((m & b.hi_z) << XY) | ((m & b.lo_z) >> XY);
+}
+
+// Isometries from signed permutation matrices acting on doubled, centred
+// coordinates u = 2x - (X-1); a matrix is kept when it maps the box onto
+// itself, and duplicates (same action on the sites) are dropped.
+std::vector<Perm> box_group(const Box &b)
+{
+    const int dims[3] = {b.X, b.Y, b.Z};
+    std::vector<Perm> out;
+    int perm[3] = {0, 1, 2};
+    do {
+        if (dims[perm[0]] != dims[0] || dims[perm[1]] != dims[1] || dims[perm[2]] != dims[2])
+            continue;
+        for (int signs = 0; signs < 8; ++signs) {
+            Perm p{};
+            for (int s = 0; s < b.N; ++s) {
+                int c[3] = {s % b.X, (s / b.X) % b.Y, s / (b.X * b.Y)};
+                int n[3];
+                for (int a = 0; a < 3; ++a) {
+                    int u = 2 * c[perm[a]] - (dims[a] - 1);
+                    if (signs & (1 << a))
+                        u = -u;
+                    n[a] = (u + dims[a] - 1) / 2;
+                }
+                p[s] = static_cast<uint8_t>(n[0] + b.X * (n[1] + b.Y * n[2]));
+            }
+            bool dup = false;
+            for (const Perm &q : out)
+                dup = dup || std::equal(q.begin(), q.begin() + b.N, p.begin());
+            if (!dup)
+                out.push_back(p);
+        }
+    } while (std::next_permutation(perm, perm + 3));
+    // identity first, so that it is always element 0 of the tied set
+    for (size_t g = 0; g < out.size(); ++g) {
+        bool id = true;
+        for (int s = 0; s < b.N; ++s)
+            id = id && out[g][s] == s;
+        if (id) {
+            std::swap(out[0], out[g]);
+            break;
+        }
+    }
+    return out;
+}
+
+Box make_box(int X, int Y, int Z)
+{
+    Box b{};
+    b.X = X; b.Y = Y; b.Z = Z; b.N = X * Y * Z;
+    b.full = (b.N == 64) ? ~uint64_t(0) : bit(b.N) - 1;
+    for (int s = 0; s < b.N; ++s) {
+        int x = s % X, y = (s / X) % Y, z = s / (X * Y);
+        if ((x + y + z) % 2 == 0) b.colour_even |= bit(s);
+        if (x > 0) b.lo_x |= bit(s);
+        if (x < X - 1) b.hi_x |= bit(s);
+        if (y > 0) b.lo_y |= bit(s);
+        if (y < Y - 1) b.hi_y |= bit(s);
+        if (z > 0) b.lo_z |= bit(s);
+        if (z < Z - 1) b.hi_z |= bit(s);
+    }
+    for (int s = 0; s < b.N; ++s)
+        b.nbr[s] = dilate(b, bit(s));
+    b.group = box_group(b);
+    return b;
+}
+
+struct Search {
+    const Box *box;
+    uint8_t path[kMaxN];
+    std::vector<uint8_t> found;      // canonical walks, N bytes each
+    uint64_t cap;                    // stop once this many canonical walks exist overall
+    std::atomic<uint64_t> *counter;
+    bool overflow = false;
+
+    bool completable(uint64_t visited, int head) const
+    {
+        const Box &b = *box;
+        uint64_t free = b.full & ~visited;
+        if (!free)
+            return true;
+        uint64_t reach = bit(head);
+        for (;;) {
+            uint64_t next = (reach | dilate(b, reach)) & (free | bit(head));
+            if (next == reach)
+                break;
+            reach = next;
+        }
+        if ((reach & free) != free)
+            return false;
+        int rem = __builtin_popcountll(free) + 1;
+        bool head_even = (b.colour_even >> head) & 1;
+        int same = __builtin_popcountll((head_even ? b.colour_even : ~b.colour_even) & free) + 1;
+        return same == (rem + 1) / 2;
+    }
+
+    void dfs(int depth, uint64_t visited, uint64_t tied)
+    {
+        const Box &b = *box;
+        if (overflow)
+            return;
+        if (depth == b.N) {
+            found.insert(found.end(), path, path + b.N);
+            if (counter->fetch_add(1) + 1 > cap)
+                overflow = true;
+            return;
+        }
+        int head = path[depth - 1];
+        uint64_t cand = b.nbr[head] & ~visited;
+        while (cand) {
+            int v = __builtin_ctzll(cand);
+            cand &= cand - 1;
+            uint64_t t = tied, keep = 0;
+            bool smaller = false;
+            while (t) {
+                int g = __builtin_ctzll(t);
+                t &= t - 1;
+                int w = b.group[g][v];
+                if (w < v) { smaller = true; break; }
+                if (w == v) keep |= bit(g);
+            }
+            if (smaller)
+                continue;
+            uint64_t nv = visited | bit(v);
+            if (!completable(nv, v))
+                continue;
+            path[depth] = static_cast<uint8_t>(v);
+            dfs(depth + 1, nv, keep);
+        }
+    }
+
+    void from(int start)
+    {
+        const Box &b = *box;
+        uint64_t tied = 0;
+        for (size_t g = 0; g < b.group.size(); ++g) {
+            int w = b.group[g][start];
+            if (w < start)
+                return;             // a symmetric start site is smaller
+            if (w == start)
+                tied |= bit(static_cast<int>(g));
+        }
+        if (!completable(bit(start), start))
+            return;
+        path[0] = static_cast<uint8_t>(start);
+        dfs(1, bit(start), tied);
+    }
+};
+
+int cmp_walk(const uint8_t *a, const uint8_t *b, int N) { return std::memcmp(a, b, N); }
+
+void canonicalise(const Box &b, const uint8_t *walk, uint8_t *out)
+{
+    uint8_t img[kMaxN];
+    bool first = true;
+    for (const Perm &p : b.group) {
+        for (int i = 0; i < b.N; ++i)
+            img[i] = p[walk[i]];
+        if (first || cmp_walk(img, out, b.N) < 0) {
+            std::memcpy(out, img, b.N);
+            first = false;
+        }
+    }
+}
+
+}  // namespace
+
+hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg)
+{
+    if (X < 1 || Y < 1 || Z < 1) {
+        *msg = "box dimensions must be >= 1";
+        return HP_EINVAL;
+    }
+    const long Nl = long(X) * Y * Z;
+    if (Nl < 2) {
+        *msg = "chain length X*Y*Z must be >= 2";
+        return HP_EINVAL;
+    }
+    if (Nl > kMaxN) {
+        *msg = "chain length X*Y*Z must be <= 36";
+        return HP_ERANGE;
+    }
+    const Box box = make_box(X, Y, Z);
+    const int N = box.N;
+
+    // ---- enumeration, start sites spread over threads -------------------
+    std::atomic<uint64_t> counter{0};
+    std::vector<Search> per_start(N);
+    const uint64_t cap = 2ull * 65535ull;   // beyond this the class ids cannot fit
+    {
+        unsigned nth = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 32u));
+        std::atomic<int> next{0};
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nth; ++t)
+            th.emplace_back([&]() {
+                for (;;) {
+                    int st = next.fetch_add(1);
+                    if (st >= N)
+                        break;
+                    Search &se = per_start[st];
+                    se.box = &box;
+                    se.cap = cap;
+                    se.counter = &counter;
+                    se.from(st);
+                }
+            });
+        for (auto &t : th)
+            t.join();
+    }
+    for (const Search &se : per_start)
+        if (se.overflow) {
+            *msg = "too many conformations for 16-bit class ids";
+            return HP_ERANGE;
+        }
+    s->X = X; s->Y = Y; s->Z = Z; s->N = N;
+    s->G = static_cast<uint32_t>(box.group.size());
+    s->walks.clear();
+    for (const Search &se : per_start)
+        s->walks.insert(s->walks.end(), se.found.begin(), se.found.end());
+    const uint32_t n_conf = static_cast<uint32_t>(s->walks.size() / N);
+    if (n_conf == 0) {
+        *msg = "box has no Hamiltonian path";
+        return HP_EINVAL;
+    }
+    if (n_conf > kMaxConf) {
+        *msg = "too many conformations";
+        return HP_ERANGE;
+    }
+    s->n_conf = n_conf;
+    s->n_walks = uint64_t(n_conf) * s->G;
+
+    // ---- reversal partners and classes -----------------------------------
+    s->rev_conf.assign(n_conf, 0);
+    {
+        std::vector<std::thread> th;
+        unsigned nth = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 32u));
+        for (unsigned t = 0; t < nth; ++t)
+            th.emplace_back([&, t]() {
+                uint8_t r[kMaxN], k[kMaxN];
+                for (uint32_t c = t; c < n_conf; c += nth) {
+                    const uint8_t *w = &s->walks[size_t(c) * N];
+                    for (int i = 0; i < N; ++i)
+                        r[i] = w[N - 1 - i];
+                    canonicalise(box, r, k);
+                    uint32_t lo = 0, hi = n_conf;
+                    while (lo < hi) {
+                        uint32_t mid = (lo + hi) / 2;
+                        if (cmp_walk(&s->walks[size_t(mid) * N], k, N) < 0)
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    bool ok = lo < n_conf && cmp_walk(&s->walks[size_t(lo) * N], k, N) == 0;
+                    s->rev_conf[c] = ok ? lo : UINT32_MAX;
+                }
+            });
+        for (auto &t : th)
+            t.join();
+    }
+    for (uint32_t c = 0; c < n_conf; ++c)
+        if (s->rev_conf[c] >= n_conf) {
+            *msg = "internal: reversed walk not found";
+            return HP_EINVAL;
+        }
+    s->c2q.assign(n_conf, 0);
+    uint32_t n_class = 0, n_selfrev = 0;
+    // a class is represented by its smaller conformation id, so numbering the
+    // representatives in ascending order ranks the class keys
+    for (uint32_t c = 0; c < n_conf; ++c) {
+        uint32_t r = s->rev_conf[c];
+        if (r >= c) {
+            if (n_class >= HP_NONE) {
+                *msg = "class count does not fit below HP_NONE";
+                return HP_ERANGE;
+            }
+            s->c2q[c] = static_cast<uint16_t>(n_class);
+            s->c2q[r] = static_cast<uint16_t>(n_class);
+            n_selfrev += (r == c);
+            ++n_class;
+        }
+    }
+    s->n_class = n_class;
+    s->n_selfrev = n_selfrev;
+    s->self_rev.assign(n_class, 0);
+    for (uint32_t c = 0; c < n_conf; ++c)
+        if (s->rev_conf[c] == c)
+            s->self_rev[s->c2q[c]] = 1;
+
+    // ---- pair table: odd separations d >= 3, by d then i -----------------
+    std::vector<int> pidx(size_t(N) * N, -1);
+    s->pairs.clear();
+    for (int d = 3; d < N; d += 2)
+        for (int i = 0; i + d < N; ++i) {
+            pidx[size_t(i) * N + i + d] = static_cast<int>(s->pairs.size() / 2);
+            s->pairs.push_back(static_cast<uint8_t>(i));
+            s->pairs.push_back(static_cast<uint8_t>(i + d));
+        }
+    s->K = static_cast<uint32_t>(s->pairs.size() / 2);
+    s->W = std::max<uint32_t>(1, (s->K + 31) / 32);
+    s->K_pad = ((s->K + 2 + 31) / 32) * 32;
+
+    // ---- contacts, bitmasks, int8 contact matrix -------------------------
+    const int edges = (X - 1) * Y * Z + X * (Y - 1) * Z + X * Y * (Z - 1);
+    s->nbp = static_cast<uint32_t>(edges - (N - 1));
+    s->contacts.assign(size_t(n_conf) * s->nbp * 2, 0);
+    s->masks.assign(size_t(n_conf) * s->W, 0);
+    const uint32_t KB = s->K_pad / 32;
+    const uint32_t n_tiles = (n_conf + kTileConf - 1) / kTileConf;
+    s->gemm_a.assign(size_t(n_tiles) * KB * 1024, 0);
+    auto a_byte = [&](uint32_t c, uint32_t k) -> int8_t & {
+        uint32_t t = c / kTileConf, col = c % kTileConf;
+        uint32_t kb = k / 32, kk = k % 32;
+        uint32_t lane = col + 32 * (kk / 16);
+        return s->gemm_a[((size_t(t) * KB + kb) * 64 + lane) * 16 + kk % 16];
+    };
+    for (uint32_t c = 0; c < n_conf; ++c) {
+        const uint8_t *w = &s->walks[size_t(c) * N];
+        int pos[kMaxN];
+        for (int i = 0; i < N; ++i)
+            pos[w[i]] = i;
+        uint32_t nc = 0;
+        for (int i = 0; i < N; ++i) {
+            uint64_t nb = box.nbr[w[i]];
+            // partners j > i+1, ascending j
+            int js[6], nj = 0;
+            while (nb) {
+                int site = __builtin_ctzll(nb);
+                nb &= nb - 1;
+                int j = pos[site];
+                if (j > i + 1)
+                    js[nj++] = j;
+            }
+            std::sort(js, js + nj);
+            for (int q = 0; q < nj; ++q) {
+                int j = js[q];
+                if (nc >= s->nbp) {
+                    *msg = "internal: contact count exceeds edges - bonds";
+                    return HP_EINVAL;
+                }
+                s->contacts[(size_t(c) * s->nbp + nc) * 2] = static_cast<uint8_t>(i);
+                s->contacts[(size_t(c) * s->nbp + nc) * 2 + 1] = static_cast<uint8_t>(j);
+                ++nc;
+                int k = pidx[size_t(i) * N + j];
+                if (k < 0) {
+                    *msg = "internal: contact with even separation";
+                    return HP_EINVAL;
+                }
+                s->masks[size_t(c) * s->W + k / 32] |= 1u << (k % 32);
+                a_byte(c, k) = static_cast<int8_t>(-128);
+            }
+        }
+        if (nc != s->nbp) {
+            *msg = "internal: contact count differs from edges - bonds";
+            return HP_EINVAL;
+        }
+        // index rows: key low bits = position of c inside its window
+        uint32_t idx = c % kWindowConf;
+        a_byte(c, s->K) = static_cast<int8_t>(idx & 127);
+        a_byte(c, s->K + 1) = static_cast<int8_t>(-static_cast<int>(idx >> 7));
+    }
+    for (uint32_t c = n_conf; c < n_tiles * kTileConf; ++c)
+        a_byte(c, s->K) = static_cast<int8_t>(-1);   // padding columns: key -1, never a winner
+
+    s->pair_rows.assign(size_t(s->K_pad) * 2, 0xFF);
+    std::copy(s->pairs.begin(), s->pairs.end(), s->pair_rows.begin());
+
+    // ---- workspace layout ---------------------------------------------------
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    WsLayout &L = s->ws;
+    L.c2q = 0;
+    L.pairs = up(L.c2q + size_t(n_conf) * 2);
+    L.masks = up(L.pairs + s->pair_rows.size());
+    L.gemm_a = up(L.masks + s->masks.size() * 4);
+    L.total = up(L.gemm_a + s->gemm_a.size());
+    return HP_OK;
+}
+
+}  // namespace hpmap

@@ -1,0 +1,142 @@
+"""Host-side checks of libhpmap that need no GPU.
+
+- every entry point declared in include/hp.h is exported by the library;
+- hp_structures (the product's own enumerator) reproduces the oracle's
+  conformations, ids, classes and contact sets exactly;
+- argument validation returns the documented error codes before any device
+  call is made.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2008_05612_amd as hp
+from paper_2008_05612_amd import _binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hp.library_path()):
+        from paper_2008_05612_amd import build
+        build.build()
+    return hp.library()
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "hp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hp_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert "hp_enumerate" in names and "hp_components" in names and "hp_neighbors" in names
+    handle = ctypes.CDLL(hp.library_path())
+    for n in names:
+        assert hasattr(handle, n), n
+
+
+def test_version_and_no_error(lib):
+    assert b"gfx950" in lib.hp_version()
+
+
+DIMS = [(2, 2, 1), (2, 3, 1), (3, 3, 1), (2, 2, 2), (3, 4, 1), (2, 2, 3), (4, 4, 1),
+        (3, 5, 1), (5, 5, 1), (2, 3, 3), (2, 4, 3), (1, 5, 1), (1, 2, 1)]
+
+
+def _compare(dims):
+    st = oracle.structures(*dims)
+    s = hp.Structures(*dims)
+    ex = s.export()
+    assert s.N == st.N and s.group_order == st.G
+    assert s.n_conf == st.n_conf and s.n_class == st.n_class
+    assert s.n_walks == st.n_walks
+    assert s.n_selfrev == int(st.self_rev.sum())
+    assert np.array_equal(ex["walks"], st.conf_keys)
+    assert np.array_equal(ex["conf_to_class"].astype(np.int64), st.conf_to_class.astype(np.int64))
+    assert np.array_equal(ex["rev_conf"].astype(np.int64), st.rev_conf.astype(np.int64))
+    assert np.array_equal(ex["self_rev"], st.self_rev)
+    nbp = s.nbp
+    if st.n_conf:
+        assert np.all(np.diff(st.ct_off) == nbp)
+    got = ex["contacts"].reshape(-1, 2)
+    ref = st.pairs.reshape(-1, 2)
+    # both list each conformation's contacts ascending by (i, j)
+    ref_sorted = np.concatenate([np.array(sorted(map(tuple, ref[st.ct_off[c]:st.ct_off[c + 1]].tolist())),
+                                          dtype=np.uint8).reshape(-1, 2) for c in range(st.n_conf)]) \
+        if nbp else np.zeros((0, 2), np.uint8)
+    assert np.array_equal(got, ref_sorted)
+    # pair table: all odd separations >= 3, each exactly once
+    pairs = ex["pairs"].astype(int)
+    N = st.N
+    want = {(i, j) for i in range(N) for j in range(i + 3, N) if (j - i) % 2 == 1}
+    assert len(pairs) == s.K == len(want) and set(map(tuple, pairs.tolist())) == want
+    assert s.W == max(1, (s.K + 31) // 32)
+    assert s.K_pad % 32 == 0 and s.K_pad >= s.K + 2 and s.K_pad - 32 < s.K + 2
+    return s
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_structures_match_oracle(lib, dims):
+    _compare(dims)
+
+
+@pytest.mark.parametrize("dims", [(6, 6, 1), (3, 3, 3), (2, 3, 4)])
+def test_structures_match_oracle_config_lattices(lib, dims):
+    s = _compare(dims)
+    if dims == (6, 6, 1):
+        assert s.n_conf == 57337 and s.nbp == 25 and s.K == 289 and s.K_pad == 320
+    if dims == (3, 3, 3):
+        assert s.n_class == 51704 and s.nbp == 28 and s.K == 156 and s.K_pad == 160
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert lib.hp_structures(0, 1, 1, ctypes.byref(h)) == -1
+    assert lib.hp_structures(1, 1, 1, ctypes.byref(h)) == -1
+    assert lib.hp_structures(7, 7, 1, ctypes.byref(h)) == -4     # N > 36
+    assert lib.hp_structures(4, 4, 1, None) == -1
+    assert b"NULL" in lib.hp_last_error()
+    s = hp.Structures(4, 4, 1)
+    fake_ws = ctypes.c_void_p(256)   # never dereferenced: validation fails first
+    # empty range, range beyond 2^N, unknown form, NULL handle/workspace
+    assert lib.hp_enumerate(s.handle, fake_ws, 1, 5, 5, None, None, None, None, None) == -1
+    assert lib.hp_enumerate(s.handle, fake_ws, 1, 0, (1 << 16) + 1, None, None, None, None,
+                            None) == -1
+    assert lib.hp_enumerate(s.handle, fake_ws, 7, 0, 16, None, None, None, None, None) == -1
+    assert lib.hp_enumerate(None, fake_ws, 1, 0, 16, None, None, None, None, None) == -1
+    assert lib.hp_enumerate(s.handle, None, 1, 0, 16, None, None, None, None, None) == -1
+    assert lib.hp_neighbors(s.handle, None, None, None, None, -1, None, None) == -1
+    assert lib.hp_neighbors(s.handle, fake_ws, None, None, None, s.n_class, None, None) == -1
+    assert lib.hp_components(s.handle, fake_ws, None, None, None, None, None) == -1
+    big = hp.Structures(6, 6, 1)
+    assert lib.hp_components(big.handle, fake_ws, fake_ws, fake_ws, None, None, None) == -4
+    assert lib.hp_upload(s.handle, fake_ws, 10, None) == -1
+    assert lib.hp_upload(s.handle, ctypes.c_void_p(257), 1 << 30, None) == -1
+    assert lib.hp_batch_workspace_bytes(0) == 0
+    assert lib.hp_enumerate_batch(None, 0, 1, fake_ws, 1 << 20, None) == -1
+    jobs = (_binding._Job * 1)()
+    jobs[0] = _binding._Job(s.handle.value, 256, 0, 16, None, None, None, None)
+    assert lib.hp_enumerate_batch(jobs, 1, 1, fake_ws, 8, None) == -1     # workspace too small
+    jobs[0] = _binding._Job(s.handle.value, 256, 16, 16, None, None, None, None)
+    assert lib.hp_enumerate_batch(jobs, 1, 1, fake_ws, 1 << 20, None) == -1   # empty job
+    g = ctypes.c_void_p()
+    assert lib.hp_graph_capture_batch(jobs, 1, 0, fake_ws, 1 << 20, ctypes.byref(g)) == -5
+
+
+def test_workspace_layout(lib):
+    s = hp.Structures(3, 3, 3)
+    n = lib.hp_workspace_bytes(s.handle)
+    n_tiles = (s.n_conf + 31) // 32
+    assert n >= s.n_conf * 2 + s.n_conf * s.W * 4 + n_tiles * 32 * s.K_pad
+    assert n % 256 == 0
