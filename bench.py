@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the HP genotype-phenotype map hot path on one MI355X.
+
+One step = the whole path over the 3x3x3 cube: ground states of all 2^27
+sequences against all 103346 conformations (int8-MFMA form: energy GEMM,
+min/unique/argmin epilogue, designability atomics), then the single-mutation
+neighbour counts (with the phi row of the most designable phenotype) and the
+neutral-network union-find over the full map.  Structures are enumerated and
+uploaded once before timing; all inputs are resident in HBM.
+
+Prints ONE JSON line.  Extra measurements (popcount form on a slice, a 6x6
+block, per-kernel times) go in the same line under "extra".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("seq×structure evals/s + full-map wall time (3×3×3, 6×6); "
+          "% int8 MFMA peak")
+PEAK_INT8_TOPS = 5000.0          # MI355X dense int8 MFMA, TOP/s
+PEAK_VALU_TOPS = 256 * 2.4e9 * 64 / 1e12   # 32-bit VALU lane-ops/s: 256 CU x 64 lanes/clk x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+class Timer:
+    """Event pair on torch's current stream, which is the stream every
+    library call in this script is enqueued on."""
+
+    def __init__(self):
+        import torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def start(self):
+        self.a.record()
+
+    def stop(self):
+        self.b.record()
+
+    def ms(self):
+        return self.a.elapsed_time(self.b)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sequence range would shard across GPUs; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2008_05612_amd as hp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dims = (3, 3, 3)
+    t0 = time.time()
+    s = hp.Structures(*dims)
+    ws = s.workspace()
+    t_struct = time.time() - t0
+    N, total, n_conf = s.N, 1 << s.N, s.n_conf
+    pairs = total * n_conf
+
+    out = torch.empty(total, dtype=torch.int16, device=dev)
+    desig = torch.zeros(s.n_class, dtype=torch.int64, device=dev)
+    nond = torch.zeros(1, dtype=torch.int64, device=dev)
+    z = lambda n: torch.zeros(n, dtype=torch.int64, device=dev)  # noqa: E731
+    neu, dele, oth, row = z(s.n_class), z(s.n_class), z(s.n_class), z(s.n_class + 1)
+    labels = torch.empty(total, dtype=torch.int32, device=dev)
+    csize = torch.empty(total, dtype=torch.int32, device=dev)
+    ncomp = torch.empty(s.n_class, dtype=torch.int32, device=dev)
+    largest = torch.empty(s.n_class, dtype=torch.int32, device=dev)
+
+    timers = {"enumerate": Timer(), "neighbors": Timer(), "components": Timer()}
+    kms = {k: [] for k in timers}
+    top = -1
+
+    def step(phi_q):
+        for t in (desig, nond, neu, dele, oth, row):
+            t.zero_()
+        timers["enumerate"].start()
+        hp.hp_enumerate(s, ws, hp.FORM_GEMM_I8, 0, total, out, None, desig, nond)
+        timers["enumerate"].stop()
+        timers["neighbors"].start()
+        hp.hp_neighbors(s, out, neu, dele, oth, phi_q, row if phi_q >= 0 else None)
+        timers["neighbors"].stop()
+        timers["components"].start()
+        hp.hp_components(s, out, labels, csize, ncomp, largest)
+        timers["components"].stop()
+
+    for i in range(max(args.warmup, 1)):
+        step(top)
+        torch.cuda.synchronize()
+        if top < 0:
+            top = int(torch.argmax(desig).item())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step(top)
+        torch.cuda.synchronize()
+        for k, t in timers.items():
+            kms[k].append(t.ms())
+    t2 = time.perf_counter()
+    ms_step = (t2 - t1) * 1e3 / args.steps
+
+    d = desig.cpu().numpy().view(np.uint64)
+    nd = int(nond.item())
+    assert int(d.sum()) + nd == total, "designability + deleterious != 2^N"
+
+    enum_ms = float(np.mean(kms["enumerate"]))
+    algo_ops = 2.0 * s.K * pairs                      # dense GEMM over the K pair rows
+    issued_ops = 2.0 * s.K_pad * pairs                # what the MFMA pipe executes
+    achieved_tops = algo_ops / (enum_ms * 1e-3) / 1e12
+    evals_per_s = pairs / (ms_step * 1e-3)
+
+    result = {
+        "metric": METRIC,
+        "value": evals_per_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {
+            "workload": "3x3x3 full map: all 2^27 sequences x 103346 conformations "
+                        "(int8-MFMA form) + single-mutation neighbour counts + union-find",
+            "lattice": "3x3x3", "N": N, "sequences": total, "n_conf": n_conf,
+            "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "form": "gemm_i8",
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved_tops,
+            "peak": PEAK_INT8_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved_tops / PEAK_INT8_TOPS,
+            "traffic": None,
+            "kernel": "k_gemm<5,4,4> (hp_enumerate, int8 MFMA)",
+            "ops_per_unit": 2 * s.K,
+        },
+    }
+    extra = {
+        "full_map_ms_3x3x3": ms_step,
+        "kernel_ms": {k: float(np.mean(v)) for k, v in kms.items()},
+        "enumerate_evals_per_s": pairs / (enum_ms * 1e-3),
+        "mfma_issued_frac": issued_ops / (enum_ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
+        "designing_fraction": float(d.sum()) / total,
+        "top_class": top,
+        "top_designability": int(d[top]),
+        "structures_s": t_struct,
+    }
+    if not args.no_extra:
+        extra.update(extra_measurements(hp, s, ws, dev))
+    result["extra"] = extra
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(dims, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+def extra_measurements(hp, s, ws, dev):
+    """Popcount form on a 2^24 slice of the cube (same GPU), and one 2^28 block
+    of the 6x6 map in both forms, with the full 6x6 time extrapolated."""
+    import torch
+    res = {}
+    n = 1 << 24
+    t = Timer()
+    for form, name in ((hp.FORM_POPCOUNT, "popcount"), (hp.FORM_GEMM_I8, "gemm_i8")):
+        hp.hp_enumerate(s, ws, form, 0, 1 << 16)
+        torch.cuda.synchronize()
+        t.start()
+        hp.hp_enumerate(s, ws, form, 0, n)
+        t.stop()
+        torch.cuda.synchronize()
+        res["3x3x3_slice_%s_evals_per_s" % name] = n * s.n_conf / (t.ms() * 1e-3)
+    res["gemm_over_popcount_3x3x3"] = (res["3x3x3_slice_gemm_i8_evals_per_s"] /
+                                       res["3x3x3_slice_popcount_evals_per_s"])
+    res["popcount_valu_frac_3x3x3"] = (res["3x3x3_slice_popcount_evals_per_s"] *
+                                       (2 * s.W + 2.5) / (PEAK_VALU_TOPS * 1e12))
+    s6 = hp.Structures(6, 6, 1)
+    ws6 = s6.workspace()
+    n6 = 1 << 28
+    d6 = torch.zeros(s6.n_class, dtype=torch.int64, device=dev)
+    for form, name in ((hp.FORM_GEMM_I8, "gemm_i8"), (hp.FORM_POPCOUNT, "popcount")):
+        hp.hp_enumerate(s6, ws6, form, 0, 1 << 16, None, None, d6)
+        torch.cuda.synchronize()
+        t.start()
+        hp.hp_enumerate(s6, ws6, form, 0, n6 if name == "gemm_i8" else n6 // 4, None, None, d6)
+        t.stop()
+        torch.cuda.synchronize()
+        nn = n6 if name == "gemm_i8" else n6 // 4
+        rate = nn * s6.n_conf / (t.ms() * 1e-3)
+        res["6x6_block_%s_evals_per_s" % name] = rate
+        res["6x6_full_map_s_extrapolated_%s" % name] = (1 << 36) * s6.n_conf / rate
+    res["6x6_gemm_i8_mfma_frac"] = (res["6x6_block_gemm_i8_evals_per_s"] * 2 * s6.K /
+                                    (PEAK_INT8_TOPS * 1e12))
+    return res
+
+
+def cpu_baseline(dims, seconds):
+    """The oracle (plain C, OpenMP over sequences) on a bounded window of the
+    same workload, on this host's cores."""
+    import oracle
+    st = oracle.structures(*dims)
+    lo = 0
+    n = 256
+    t0 = time.perf_counter()
+    oracle.ground_states(st, lo, lo + n)
+    dt = time.perf_counter() - t0
+    n = int(max(256, min(1 << 20, n * seconds / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.ground_states(st, lo, lo + n)
+    dt = time.perf_counter() - t0
+    return {"value": n * st.n_conf / dt, "unit": "evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "3x3x3, sequences [0, %d) x all %d conformations, %.1f s" % (n, st.n_conf, dt)}
+
+
+if __name__ == "__main__":
+    main()

@@ -171,6 +171,37 @@ hp_status hp_graph_launch(hp_graph *g, void *stream);
 void hp_graph_free(hp_graph *g);
 
 /*
+ * Tile shapes of the int8 form and their autotuning.  Several shapes are
+ * compiled per product depth K_pad (hp_info.K_pad).  A shape is (T, NW, mode):
+ * T sequence tiles of 32 per wave, NW waves per workgroup, and mode 0 when
+ * the contact-matrix tiles are staged through LDS by the workgroup or 1 when
+ * every wave loads them from global memory itself.  The choice is
+ * process-wide per K_pad and shared by all threads; the first listed shape is
+ * the default.  The launch configuration never changes results, only speed.
+ *   hp_gemm_shape_count  number of compiled shapes for K_pad (0 if none);
+ *   hp_gemm_shape_info   describe shape idx (any out pointer may be NULL);
+ *   hp_gemm_select       make shape idx the choice for K_pad;
+ *   hp_gemm_selected     current choice for K_pad (-1 if none compiled);
+ *   hp_autotune          time every shape of the handle's K_pad on sequences
+ *                        [seq_lo, seq_lo + n_seq) (no outputs written,
+ *                        `repeats` launches each after one warm-up), select
+ *                        the fastest, write per-shape milliseconds to ms[]
+ *                        (hp_gemm_shape_count entries, may be NULL) and its
+ *                        index to *best (may be NULL).  Synchronises `stream`.
+ *                        If the environment variable HP_TUNE_CACHE names a
+ *                        file, the choice is recorded there and read back by
+ *                        later processes on first use of that K_pad.
+ * Errors: HP_EINVAL for an unknown shape, NULL handle/workspace or a range
+ * outside [0, 2^N); HP_EDEVICE for a failed launch.
+ */
+int hp_gemm_shape_count(uint32_t K_pad);
+hp_status hp_gemm_shape_info(uint32_t K_pad, int idx, int *T, int *NW, int *mode);
+hp_status hp_gemm_select(uint32_t K_pad, int idx);
+int hp_gemm_selected(uint32_t K_pad);
+hp_status hp_autotune(const hp_structs *s, const void *d_ws, uint64_t seq_lo, uint64_t n_seq,
+                      int repeats, float *ms, int *best, void *stream);
+
+/*
  * hp_neighbors -- single-point-mutation statistics of a complete map
  * (Eq. 2: phi_pq; robustness rho_q = phi_qq; phi_del).  d_map holds the
  * phenotype of all 2^N sequences.  For every designing genotype g with

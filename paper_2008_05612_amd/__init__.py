@@ -16,7 +16,11 @@ from ._binding import (  # noqa: F401
     Structures,
     hp_components,
     hp_enumerate,
+    hp_autotune,
     hp_enumerate_batch,
+    hp_gemm_select,
+    hp_gemm_selected,
+    hp_gemm_shapes,
     hp_graph_capture_batch,
     hp_neighbors,
     hp_structures,

@@ -83,6 +83,13 @@ def library():
         "hp_graph_free": (None, [vp]),
         "hp_neighbors": (st, [vp, vp, vp, vp, vp, i32, vp, vp]),
         "hp_components": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "hp_gemm_shape_count": (ctypes.c_int, [ctypes.c_uint32]),
+        "hp_gemm_shape_info": (st, [ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "hp_gemm_select": (st, [ctypes.c_uint32, ctypes.c_int]),
+        "hp_gemm_selected": (ctypes.c_int, [ctypes.c_uint32]),
+        "hp_autotune": (st, [vp, vp, u64, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_int), vp]),
         "hp_last_error": (ctypes.c_char_p, []),
         "hp_version": (ctypes.c_char_p, []),
     }
@@ -301,3 +308,37 @@ def hp_components(s: Structures, phen_map, labels, compsize, ncomp=None, largest
         _ptr(compsize, torch.int32, n, "compsize"), _ptr(ncomp, torch.int32, s.n_class, "ncomp"),
         _ptr(largest, torch.int32, s.n_class, "largest"), _stream_handle(stream)),
         "hp_components")
+
+
+def hp_gemm_shapes(K_pad: int):
+    """Compiled tile shapes of the int8 form for one product depth, as
+    (T, NW, mode) tuples in library order."""
+    L = library()
+    out = []
+    for i in range(L.hp_gemm_shape_count(K_pad)):
+        T, NW, mode = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(L.hp_gemm_shape_info(K_pad, i, ctypes.byref(T), ctypes.byref(NW),
+                                    ctypes.byref(mode)), "hp_gemm_shape_info")
+        out.append((T.value, NW.value, mode.value))
+    return out
+
+
+def hp_gemm_select(K_pad: int, idx: int):
+    _check(library().hp_gemm_select(K_pad, idx), "hp_gemm_select")
+
+
+def hp_gemm_selected(K_pad: int) -> int:
+    return int(library().hp_gemm_selected(K_pad))
+
+
+def hp_autotune(s: Structures, ws, seq_lo: int, n_seq: int, repeats: int = 2, stream=None):
+    """Time every compiled shape of s.K_pad on [seq_lo, seq_lo+n_seq), select the
+    fastest; returns (best index, list of milliseconds per shape)."""
+    import torch
+    n = library().hp_gemm_shape_count(s.K_pad)
+    ms = (ctypes.c_float * max(n, 1))()
+    best = ctypes.c_int(-1)
+    _check(library().hp_autotune(s.handle, _ptr(ws, torch.uint8, None, "workspace"), seq_lo,
+                                 n_seq, repeats, ms, ctypes.byref(best), _stream_handle(stream)),
+           "hp_autotune")
+    return best.value, [float(ms[i]) for i in range(n)]

@@ -15,7 +15,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhpmap.so")
-SOURCES = ["structures.cpp", "capi.cpp", "kernels_enum.hip", "kernels_net.hip"]
+SOURCES = ["structures.cpp", "capi.cpp", "runtime.cpp", "kernels_popcount.hip",
+           "gemm_kb1_4.hip", "gemm_kb5.hip", "gemm_kb6_10.hip", "gemm_batch.hip",
+           "kernels_net.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -26,6 +28,9 @@ FLAGS = [
     "-fPIC",
     # packed fp32 VALU ops are kept out of every code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs where register pressure allows, so
+    # the epilogue reads them without v_accvgpr_read copies
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I" + os.path.join(ROOT, "include"),
     "-I" + CSRC,
     "-Wall",

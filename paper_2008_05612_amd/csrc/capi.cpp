@@ -26,30 +26,6 @@ hp_status device_fail(hipError_t e, const char *what)
     return fail(HP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-EnumJob make_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64_t hi, uint16_t *out,
-                 int32_t *emin, uint64_t *desig, uint64_t *nondesign)
-{
-    const char *base = static_cast<const char *>(d_ws);
-    EnumJob j{};
-    j.c2q = reinterpret_cast<const uint16_t *>(base + s->ws.c2q);
-    j.pairs = reinterpret_cast<const uint8_t *>(base + s->ws.pairs);
-    j.masks = reinterpret_cast<const uint32_t *>(base + s->ws.masks);
-    j.gemm_a = reinterpret_cast<const int8_t *>(base + s->ws.gemm_a);
-    j.out = out;
-    j.emin = emin;
-    j.desig = reinterpret_cast<unsigned long long *>(desig);
-    j.nondesign = reinterpret_cast<unsigned long long *>(nondesign);
-    j.lo = lo;
-    j.hi = hi;
-    j.N = s->N;
-    j.K = int32_t(s->K);
-    j.W = int32_t(s->W);
-    j.KB = int32_t(s->K_pad / 32);
-    j.n_conf = int32_t(s->n_conf);
-    j.n_tiles = int32_t((s->n_conf + kTileConf - 1) / kTileConf);
-    return j;
-}
-
 hp_status check_range(const hp_structs *s, const void *d_ws, uint64_t lo, uint64_t hi)
 {
     if (!s)
@@ -83,8 +59,7 @@ hp_status plan_batch(const hp_job *jobs, int njobs, size_t ws_bytes, BatchPlan *
             return st;
         kb_max = std::max(kb_max, int(jobs[i].structs->K_pad / 32));
     }
-    const GemmShape sh = kb_max <= 5 ? GemmShape{4, 4} : GemmShape{2, 4};
-    const uint64_t per = gemm_seqs_per_item(sh);
+    const uint64_t per = gemm_batch_seqs_per_item(kb_max);
     std::vector<int64_t> start(njobs + 1, 0);
     for (int i = 0; i < njobs; ++i) {
         const uint64_t n = jobs[i].seq_hi - jobs[i].seq_lo;
@@ -101,7 +76,7 @@ hp_status plan_batch(const hp_job *jobs, int njobs, size_t ws_bytes, BatchPlan *
     std::memcpy(plan->host.data(), &hdr, sizeof(hdr));
     EnumJob *ej = reinterpret_cast<EnumJob *>(plan->host.data() + sizeof(BatchHeader));
     for (int i = 0; i < njobs; ++i)
-        ej[i] = make_job(jobs[i].structs, jobs[i].d_ws, jobs[i].seq_lo, jobs[i].seq_hi,
+        ej[i] = make_enum_job(jobs[i].structs, jobs[i].d_ws, jobs[i].seq_lo, jobs[i].seq_hi,
                          jobs[i].d_out, jobs[i].d_emin, jobs[i].d_designability,
                          jobs[i].d_nondesign);
     std::memcpy(plan->host.data() + sizeof(BatchHeader) + sizeof(EnumJob) * njobs, start.data(),
@@ -112,6 +87,30 @@ hp_status plan_batch(const hp_job *jobs, int njobs, size_t ws_bytes, BatchPlan *
 }
 
 }  // namespace
+
+EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64_t hi, uint16_t *out,
+                 int32_t *emin, uint64_t *desig, uint64_t *nondesign)
+{
+    const char *base = static_cast<const char *>(d_ws);
+    EnumJob j{};
+    j.c2q = reinterpret_cast<const uint16_t *>(base + s->ws.c2q);
+    j.pairs = reinterpret_cast<const uint8_t *>(base + s->ws.pairs);
+    j.masks = reinterpret_cast<const uint32_t *>(base + s->ws.masks);
+    j.gemm_a = reinterpret_cast<const int8_t *>(base + s->ws.gemm_a);
+    j.out = out;
+    j.emin = emin;
+    j.desig = reinterpret_cast<unsigned long long *>(desig);
+    j.nondesign = reinterpret_cast<unsigned long long *>(nondesign);
+    j.lo = lo;
+    j.hi = hi;
+    j.N = s->N;
+    j.K = int32_t(s->K);
+    j.W = int32_t(s->W);
+    j.KB = int32_t(s->K_pad / 32);
+    j.n_conf = int32_t(s->n_conf);
+    j.n_tiles = int32_t((s->n_conf + kTileConf - 1) / kTileConf);
+    return j;
+}
 
 hp_status fail(hp_status st, const std::string &msg)
 {
@@ -239,13 +238,15 @@ hp_status hp_enumerate(const hp_structs *s, const void *d_ws, int form, uint64_t
     if (form != HP_FORM_POPCOUNT && form != HP_FORM_GEMM_I8)
         return fail(HP_EINVAL, "unknown kernel form");
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    const GemmShape shape = default_gemm_shape(int(s->K_pad / 32));
+    const GemmVariant *var = nullptr;
+    if (form == HP_FORM_GEMM_I8 && !(var = gemm_selected_variant(int(s->K_pad / 32))))
+        return fail(HP_EUNSUPPORTED, "no compiled int8 kernel for this K_pad");
     for (uint64_t lo = seq_lo; lo < seq_hi; lo += kBlockSeqs) {
         const uint64_t hi = std::min(seq_hi, lo + kBlockSeqs);
-        EnumJob j = make_job(s, d_ws, lo, hi, d_out ? d_out + (lo - seq_lo) : nullptr,
+        EnumJob j = make_enum_job(s, d_ws, lo, hi, d_out ? d_out + (lo - seq_lo) : nullptr,
                              d_emin ? d_emin + (lo - seq_lo) : nullptr, d_designability,
                              d_nondesign);
-        hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs) : launch_gemm(j, shape, hs);
+        hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs) : var->launch(j, hs);
         if (e != hipSuccess)
             return device_fail(e, "hp_enumerate launch");
     }

@@ -1,0 +1,140 @@
+// Device helpers shared by the ground-state kernels of libhpmap (internal).
+//
+// Running state of a sequence is a pair of 32-bit keys (best, second).  A key
+// orders first by the number n of H-H contacts and then by conformation, so
+// the largest key is a minimum-energy conformation (E = -n, Eq. 1 with
+// E_HH = -1) and the second-largest key has the same n exactly when the
+// minimum is shared, i.e. when the sequence does not fold (Methods, end of
+// "HP and MJ lattice models").  Keys are non-negative: global keys are
+// (n << 17) | (conformation + 1) and 0 stands for "no conformation", so
+// signed and unsigned comparisons agree.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "hp_internal.h"
+#include "kernels.h"
+
+namespace hpmap {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kWinShift = 14;   // window key of the int8 form = (n << 14) | idx
+
+// Median of three, written as max(min(a, b), min(max(a, b), c)), which the
+// backend selects as one v_med3_i32.  No inline assembly here: the compiler
+// must see the instruction to insert the wait states between an MFMA and the
+// VALU reads of its result registers.
+__device__ __forceinline__ int med3_i32(int a, int b, int c)
+{
+    return max(min(a, b), min(max(a, b), c));
+}
+
+// (b, s) is the running top-2, b >= s >= 0.  Absorb keys k1, k2 >= 0.
+// The new best uses unsigned comparisons and the median signed ones (equal
+// orders on non-negative keys): being different operations, the compiler
+// cannot merge their common max(b, k1), and each selects to a single
+// three-operand instruction (v_max3_u32, v_med3_i32); the second then folds
+// two medians per v_max3_i32.
+__device__ __forceinline__ void top2_add2(int &b, int &s, int k1, int k2)
+{
+    const int m = med3_i32(b, k1, k2);   // second largest of {b, k1, k2}
+    b = int(max(max(unsigned(b), unsigned(k1)), unsigned(k2)));
+    s = max(s, m);
+}
+
+__device__ __forceinline__ void top2_add1(int &b, int &s, int k)
+{
+    s = max(s, min(b, k));
+    b = max(b, k);
+}
+
+__device__ __forceinline__ void top2_merge(int &b, int &s, int b2, int s2)
+{
+    s = max(min(b, b2), max(s, s2));
+    b = max(b, b2);
+}
+
+// Window key -> global key (0 stays 0): (k & 16383) is the position + 1.
+__device__ __forceinline__ int window_to_global(int k, int conf_base)
+{
+    const int g = ((k >> kWinShift) << kKeyConfBits) | (conf_base + (k & ((1 << kWinShift) - 1)));
+    return k == 0 ? 0 : g;
+}
+
+// Final decision for one sequence and the per-sequence outputs.
+__device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, bool valid, int gb,
+                                                int gs, bool count_lane)
+{
+    const int nb = gb >> kKeyConfBits;
+    const int ns = gs >> kKeyConfBits;
+    const bool uniq = gs == 0 || nb != ns;   // no second conformation, or a lower one
+    uint16_t q = HP_NONE;
+    if (valid && uniq)   // the clamp keeps the table read in bounds for any key
+        q = j.c2q[min(max((gb & int(kMaxConf)) - 1, 0), j.n_conf - 1)];
+    if (valid) {
+        if (j.out)
+            j.out[s - j.lo] = q;
+        if (j.emin)
+            j.emin[s - j.lo] = -nb;
+        if (uniq && j.desig)
+            atomicAdd(&j.desig[q], 1ull);
+    }
+    const unsigned long long del = __ballot(valid && !uniq);
+    if (count_lane && j.nondesign && del)
+        atomicAdd(j.nondesign, (unsigned long long)__popcll(del));
+}
+
+// B-operand fragments of one lane for T sequences: bytes of product rows
+// kbase .. kbase+15 with kbase = 32 kb + 16 half (byte q of a fragment is row
+// kbase + q).  Row k < K is the pair (i, i + d) of the k-th odd separation
+// d >= 3 in (d, i) order, and its byte is 0x80 * h_i h_{i+d}; row K is the
+// constant 0x01 and row K+1 the constant 0x80 (the index rows); rows beyond
+// are 0.  The pair of the first row is found by walking the run lengths
+// N - d; consecutive rows then advance (d, i) incrementally, so no table is
+// read.
+template <int KB, int T>
+__device__ __forceinline__ void p_fragments(const uint64_t (&s)[T], int half, int N, int K,
+                                            v4i (&pf)[T][KB])
+{
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const int kbase = kb * 32 + half * 16;
+        int d = 3, i = kbase;
+        while (d < N && i >= N - d) {   // skip whole runs of separation d
+            i -= N - d;
+            d += 2;
+        }
+        uint32_t w[T][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                w[t][q] = 0;
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                const int k = kbase + 4 * q + bb;
+                const uint32_t c = k == K ? 0x01u : (k == K + 1 ? 0x80u : 0u);
+                const bool real = k < K;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const uint32_t bit = real ? uint32_t((s[t] >> i) & (s[t] >> (i + d)) & 1u) : 0u;
+                    w[t][q] |= ((bit << 7) | c) << (8 * bb);
+                }
+                ++i;                       // next row: next i, or the next run
+                if (i + d >= N) {
+                    i = 0;
+                    d += 2;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            pf[t][kb] = v4i{int(w[t][0]), int(w[t][1]), int(w[t][2]), int(w[t][3])};
+    }
+}
+
+}  // namespace hpmap

@@ -1,0 +1,210 @@
+// int8-MFMA form of the ground-state search (internal templates; instantiated
+// per product depth in gemm_kb*.hip).
+//
+// Contacts on the bipartite lattice join monomers whose separation j - i is
+// odd and >= 3; index these K pairs as k.  For sequence s, P_k(s) = h_i h_j
+// and C_k(c) = 1 iff pair k is a contact of conformation c, so the number of
+// H-H contacts is n(s,c) = sum_k P_k(s) C_k(c): a K-deep integer matrix
+// product (the energy of Eq. 1 with E_HH = -1 is -n).
+//
+// Operands of v_mfma_i32_32x32x32_i8: A = C^T, 32 conformations x 32 rows per
+// block, stored pre-swizzled so that lane l's 16 bytes are one load; B = P for
+// 32 sequences, generated in registers once per sequence tile and held for
+// the whole sweep over conformations.  Entries are -128 on both sides, so each
+// H-H contact adds 16384.  Rows K and K+1 carry u = 1 + the conformation's
+// position within its window of 16352 conformations (P = 1, C = u & 127 and
+// P = -128, C = -(u >> 7)), so the accumulator IS the window key
+// 16384 n + u and the epilogue needs no index arithmetic: per two values one
+// med3, one max3 and half of a max3.  Padding columns hold key 0.
+//
+// Two staging modes for A:
+//   kLds    : the workgroup copies each conformation tile global -> LDS
+//             (double-buffered, one barrier per tile) and every wave reads its
+//             fragments from LDS;
+//   kDirect : every wave loads its fragments straight from global memory
+//             (L1/L2-resident, all waves sweep the same tiles) into registers,
+//             one tile ahead; no LDS, no barriers.
+#pragma once
+
+#include "device_common.h"
+
+namespace hpmap {
+
+enum { kLds = 0, kDirect = 1 };
+
+template <int KB, int NW>
+struct TileStage {
+    static constexpr int kVecs = KB * 64;                       // 16-byte vectors per tile
+    static constexpr int kPer = (kVecs + NW * 64 - 1) / (NW * 64);
+    v4i v[kPer];
+
+    __device__ __forceinline__ void load(const v4i *__restrict__ A, int tile)
+    {
+        const v4i *src = A + size_t(tile) * kVecs;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int i = threadIdx.x + r * NW * 64;
+            if (kVecs % (NW * 64) == 0 || i < kVecs)
+                v[r] = src[i];
+        }
+    }
+    __device__ __forceinline__ void store(v4i *dst) const
+    {
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int i = threadIdx.x + r * NW * 64;
+            if (kVecs % (NW * 64) == 0 || i < kVecs)
+                dst[i] = v[r];
+        }
+    }
+};
+
+template <int KB, int T>
+__device__ __forceinline__ void mma_tile(const v4i (&a)[KB], const v4i (&pf)[T][KB], v16i (&acc)[T])
+{
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const v16i zero = {};
+            acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[kb], pf[t][kb], kb == 0 ? zero : acc[t],
+                                                            0, 0, 0);
+        }
+}
+
+template <int T>
+__device__ __forceinline__ void epilogue_tile(const v16i (&acc)[T], int (&b)[T], int (&sc)[T])
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; r += 2)
+            top2_add2(b[t], sc[t], acc[t][r], acc[t][r + 1]);
+}
+
+template <int T>
+__device__ __forceinline__ void fold_window(int (&b)[T], int (&sc)[T], int (&gb)[T], int (&gs)[T],
+                                            int conf_base)
+{
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        top2_merge(gb[t], gs[t], window_to_global(b[t], conf_base),
+                   window_to_global(sc[t], conf_base));
+        b[t] = sc[t] = 0;
+    }
+}
+
+// One workgroup scores NW*T*32 consecutive sequences starting at seq0_wg
+// against every conformation tile.  lds holds 2*KB*64 vectors (kLds only).
+template <int KB, int T, int NW, int MODE>
+__device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4i *lds)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const uint64_t seq0 = seq0_wg + uint64_t(wave) * (T * 32);
+    const v4i *__restrict__ A = reinterpret_cast<const v4i *>(j.gemm_a);
+
+    v4i pf[T][KB];
+    {
+        uint64_t seqs[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            seqs[t] = seq0 + t * 32 + col;
+        p_fragments<KB, T>(seqs, half, j.N, j.K, pf);
+    }
+
+    int b[T], sc[T], gb[T], gs[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+        b[t] = sc[t] = gb[t] = gs[t] = 0;
+
+    const int n_tiles = j.n_tiles;
+    int wend = min(kWindowTiles, n_tiles);
+    int conf_base = 0;
+
+    if constexpr (MODE == kLds) {
+        TileStage<KB, NW> stg;
+        stg.load(A, 0);
+        stg.store(lds);
+        __syncthreads();
+        for (int tile = 0; tile < n_tiles; ++tile) {
+            const bool more = tile + 1 < n_tiles;
+            if (more)
+                stg.load(A, tile + 1);
+            const v4i *cur = lds + (tile & 1) * (KB * 64);
+            v4i a[KB];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                a[kb] = cur[kb * 64 + lane];
+            v16i acc[T];
+            mma_tile<KB, T>(a, pf, acc);
+            epilogue_tile<T>(acc, b, sc);
+            if (tile + 1 == wend) {
+                fold_window<T>(b, sc, gb, gs, conf_base);
+                conf_base += kWindowConf;
+                wend = min(wend + kWindowTiles, n_tiles);
+            }
+            if (more)
+                stg.store(lds + ((tile + 1) & 1) * (KB * 64));
+            __syncthreads();
+        }
+    } else {
+        v4i a[KB], an[KB];
+        const v4i *src = A + lane;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+            a[kb] = src[kb * 64];
+        for (int tile = 0; tile < n_tiles; ++tile) {
+            const int nt = min(tile + 1, n_tiles - 1);   // re-reads the last tile: in bounds
+            const v4i *nsrc = A + size_t(nt) * (KB * 64) + lane;
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                an[kb] = nsrc[kb * 64];
+            v16i acc[T];
+            mma_tile<KB, T>(a, pf, acc);
+            epilogue_tile<T>(acc, b, sc);
+            if (tile + 1 == wend) {
+                fold_window<T>(b, sc, gb, gs, conf_base);
+                conf_base += kWindowConf;
+                wend = min(wend + kWindowTiles, n_tiles);
+            }
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                a[kb] = an[kb];
+        }
+    }
+
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int ob = __shfl_xor(gb[t], 32);
+        const int os = __shfl_xor(gs[t], 32);
+        top2_merge(gb[t], gs[t], ob, os);
+        const uint64_t s = seq0 + t * 32 + col;
+        finish_sequence(j, s, half == 0 && s < j.hi, gb[t], gs[t], lane == 0);
+    }
+}
+
+template <int KB, int T, int NW, int MODE>
+__global__ __launch_bounds__(NW * 64) void k_gemm(EnumJob j)
+{
+    __shared__ v4i lds[MODE == kLds ? 2 * KB * 64 : 1];
+    const uint64_t seq0 = j.lo + uint64_t(blockIdx.x) * (NW * T * 32);
+    gemm_body<KB, T, NW, MODE>(j, seq0, lds);
+}
+
+template <int KB, int T, int NW, int MODE>
+hipError_t launch_gemm_variant(const EnumJob &j, hipStream_t st)
+{
+    const uint64_t n = j.hi - j.lo;
+    const uint64_t per = uint64_t(T) * NW * 32;
+    const dim3 grid(unsigned((n + per - 1) / per));
+    hipLaunchKernelGGL((k_gemm<KB, T, NW, MODE>), grid, dim3(NW * 64), 0, st, j);
+    return hipGetLastError();
+}
+
+#define HP_GEMM_VARIANT(KB, T, NW, MODE) \
+    GemmVariant{KB, T, NW, MODE, &launch_gemm_variant<KB, T, NW, MODE>}
+
+}  // namespace hpmap

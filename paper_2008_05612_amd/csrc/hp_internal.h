@@ -13,15 +13,19 @@ namespace hpmap {
 
 constexpr int kMaxN = 36;            // sequences are 64-bit, ids 16-bit
 constexpr int kTileConf = 32;        // conformations per MFMA tile (rows of A)
-constexpr int kWindowConf = 16384;   // conformations per key window of the int8 form
-constexpr int kWindowTiles = kWindowConf / kTileConf;
-constexpr int kKeyConfBits = 17;     // global key = (n_HH << 17) | conformation id
-constexpr uint32_t kMaxConf = 1u << kKeyConfBits;
+// Keys of the running minimum search are non-negative; 0 means "no
+// conformation".  Global key = (n_HH << 17) | (conformation + 1); window key of
+// the int8 form = (n_HH << 14) | (position in window + 1), with windows of 511
+// tiles so that position + 1 stays below 2^14.
+constexpr int kWindowTiles = 511;
+constexpr int kWindowConf = kWindowTiles * kTileConf;   // 16352
+constexpr int kKeyConfBits = 17;
+constexpr uint32_t kMaxConf = (1u << kKeyConfBits) - 1;
 
 // Byte offsets of the packed tables inside the device workspace.
 struct WsLayout {
     size_t c2q = 0;      // uint16_t[n_conf]
-    size_t pairs = 0;    // uint8_t[K_pad][2]
+    size_t pairs = 0;    // uint8_t[K_pad][4] row table (i, j, constant, 0)
     size_t masks = 0;    // uint32_t[n_conf][W]
     size_t gemm_a = 0;   // int8_t[n_tiles][K_pad/32][64 lanes][16]
     size_t total = 0;
@@ -42,7 +46,7 @@ struct hp_structs {
     std::vector<uint8_t> contacts;    // n_conf * nbp * 2, (i, j) ascending
     std::vector<uint32_t> masks;      // n_conf * W contact bitmasks
     std::vector<int8_t> gemm_a;       // int8 contact matrix in MFMA A-operand order
-    std::vector<uint8_t> pair_rows;   // K_pad * 2 (rows >= K are 0xFF markers)
+    std::vector<uint8_t> pair_rows;   // K_pad * 4: (i, j, constant, 0) per product row
     hpmap::WsLayout ws;
 };
 
@@ -50,6 +54,11 @@ namespace hpmap {
 
 // Host enumeration (structures.cpp).  Returns HP_OK or an error with msg set.
 hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg);
+
+struct EnumJob;
+// Kernel-side descriptor of one enumeration over [lo, hi) (capi.cpp).
+EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64_t hi,
+                      uint16_t *out, int32_t *emin, uint64_t *desig, uint64_t *nondesign);
 
 // Error plumbing (capi.cpp).
 hp_status fail(hp_status st, const std::string &msg);

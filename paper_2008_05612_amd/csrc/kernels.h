@@ -11,7 +11,7 @@ namespace hpmap {
 // arguments (single launches) or into the batch work list (device memory).
 struct EnumJob {
     const uint16_t *c2q;            // conformation -> class
-    const uint8_t *pairs;           // K_pad x 2 pair table (rows >= K unused)
+    const uint8_t *pairs;           // K_pad x 4 row table (i, j, constant, 0)
     const uint32_t *masks;          // n_conf x W contact bitmasks
     const int8_t *gemm_a;           // int8 contact matrix, MFMA A-operand order
     uint16_t *out;                  // phenotype per sequence, or null
@@ -31,17 +31,26 @@ struct BatchHeader {
     int32_t kb_max;
 };
 
-// Tile shape of the int8 form: sequence tiles of 32 per wave (T of them),
-// NW waves per workgroup.
-struct GemmShape {
-    int T;
-    int NW;
+// One compiled tile shape of the int8 form: KB = K_pad/32 product depth, T
+// sequence tiles of 32 per wave, NW waves per workgroup, A staged through
+// LDS (mode 0) or loaded per wave from global memory (mode 1).
+struct GemmVariant {
+    int KB, T, NW, mode;
+    hipError_t (*launch)(const EnumJob &j, hipStream_t st);
 };
 
+// Compiled variants, grouped by the translation unit that instantiates them.
+int gemm_variants_kb1_4(const GemmVariant **out);
+int gemm_variants_kb5(const GemmVariant **out);
+int gemm_variants_kb6_10(const GemmVariant **out);
+
+// Shape used for product depth KB (process-wide choice; default: first listed).
+const GemmVariant *gemm_selected_variant(int KB);
+
 hipError_t launch_popcount(const EnumJob &j, hipStream_t st);
-hipError_t launch_gemm(const EnumJob &j, GemmShape shape, hipStream_t st);
-GemmShape default_gemm_shape(int KB);
-uint64_t gemm_seqs_per_item(GemmShape shape);
+// Sequences per work item of the persistent batched kernel for a given
+// deepest job (its tile shape is fixed per depth class).
+uint64_t gemm_batch_seqs_per_item(int kb_max);
 // Batched persistent launch: header at d_ws, then EnumJob[njobs], then
 // int64 item_start[njobs + 1].
 hipError_t launch_gemm_batch(void *d_batch_ws, int kb_max, int n_items, hipStream_t st);

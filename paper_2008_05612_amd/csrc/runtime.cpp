@@ -1,0 +1,237 @@
+// Runtime pieces of libhpmap around the int8 kernels: the registry of compiled
+// tile shapes, the process-wide shape choice per product depth, the
+// autotuner that times the shapes on the device, and its on-disk cache.
+//
+// Cache file (path in the HP_TUNE_CACHE environment variable, optional): one
+// line per depth, "gfx950 <K_pad> <T> <NW> <mode>", written by hp_autotune and
+// read the first time a depth is launched.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hp_internal.h"
+#include "kernels.h"
+
+namespace hpmap {
+
+namespace {
+
+constexpr int kMaxKB = 10;
+
+struct Registry {
+    std::vector<GemmVariant> by_kb[kMaxKB + 1];
+    std::atomic<int> selected[kMaxKB + 1];
+    std::once_flag cache_once;
+
+    Registry()
+    {
+        for (auto &s : selected)
+            s.store(0);
+        int (*groups[])(const GemmVariant **) = {gemm_variants_kb1_4, gemm_variants_kb5,
+                                                 gemm_variants_kb6_10};
+        for (auto g : groups) {
+            const GemmVariant *v = nullptr;
+            int n = g(&v);
+            for (int i = 0; i < n; ++i)
+                if (v[i].KB >= 1 && v[i].KB <= kMaxKB)
+                    by_kb[v[i].KB].push_back(v[i]);
+        }
+    }
+};
+
+Registry &registry()
+{
+    static Registry r;
+    return r;
+}
+
+int find_shape(int KB, int T, int NW, int mode)
+{
+    const auto &v = registry().by_kb[KB];
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i].T == T && v[i].NW == NW && v[i].mode == mode)
+            return int(i);
+    return -1;
+}
+
+void load_cache()
+{
+    const char *path = std::getenv("HP_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return;
+    char arch[32];
+    int kpad, T, NW, mode;
+    while (std::fscanf(f, "%31s %d %d %d %d", arch, &kpad, &T, &NW, &mode) == 5) {
+        if (std::strcmp(arch, "gfx950") != 0 || kpad % 32 != 0)
+            continue;
+        const int KB = kpad / 32;
+        if (KB < 1 || KB > kMaxKB)
+            continue;
+        const int idx = find_shape(KB, T, NW, mode);
+        if (idx >= 0)
+            registry().selected[KB].store(idx);
+    }
+    std::fclose(f);
+}
+
+void store_cache(int KB, const GemmVariant &v)
+{
+    const char *path = std::getenv("HP_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    // keep other depths' lines, replace this depth's
+    std::vector<std::string> keep;
+    if (FILE *f = std::fopen(path, "r")) {
+        char line[256];
+        while (std::fgets(line, sizeof line, f)) {
+            char arch[32];
+            int kpad;
+            if (std::sscanf(line, "%31s %d", arch, &kpad) == 2 && std::strcmp(arch, "gfx950") == 0 &&
+                kpad == KB * 32)
+                continue;
+            keep.emplace_back(line);
+        }
+        std::fclose(f);
+    }
+    if (FILE *f = std::fopen(path, "w")) {
+        for (const auto &l : keep)
+            std::fputs(l.c_str(), f);
+        std::fprintf(f, "gfx950 %d %d %d %d\n", KB * 32, v.T, v.NW, v.mode);
+        std::fclose(f);
+    }
+}
+
+}  // namespace
+
+const GemmVariant *gemm_selected_variant(int KB)
+{
+    if (KB < 1 || KB > kMaxKB)
+        return nullptr;
+    Registry &r = registry();
+    std::call_once(r.cache_once, load_cache);
+    const auto &v = r.by_kb[KB];
+    if (v.empty())
+        return nullptr;
+    int idx = r.selected[KB].load();
+    if (idx < 0 || idx >= int(v.size()))
+        idx = 0;
+    return &v[idx];
+}
+
+}  // namespace hpmap
+
+using namespace hpmap;
+
+extern "C" {
+
+int hp_gemm_shape_count(uint32_t K_pad)
+{
+    if (K_pad % 32 != 0 || K_pad / 32 < 1 || K_pad / 32 > uint32_t(kMaxKB))
+        return 0;
+    return int(registry().by_kb[K_pad / 32].size());
+}
+
+hp_status hp_gemm_shape_info(uint32_t K_pad, int idx, int *T, int *NW, int *mode)
+{
+    const int n = hp_gemm_shape_count(K_pad);
+    if (idx < 0 || idx >= n)
+        return fail(HP_EINVAL, "no such tile shape for this K_pad");
+    const GemmVariant &v = registry().by_kb[K_pad / 32][idx];
+    if (T)
+        *T = v.T;
+    if (NW)
+        *NW = v.NW;
+    if (mode)
+        *mode = v.mode;
+    return HP_OK;
+}
+
+hp_status hp_gemm_select(uint32_t K_pad, int idx)
+{
+    const int n = hp_gemm_shape_count(K_pad);
+    if (idx < 0 || idx >= n)
+        return fail(HP_EINVAL, "no such tile shape for this K_pad");
+    Registry &r = registry();
+    std::call_once(r.cache_once, load_cache);
+    r.selected[K_pad / 32].store(idx);
+    return HP_OK;
+}
+
+int hp_gemm_selected(uint32_t K_pad)
+{
+    if (hp_gemm_shape_count(K_pad) == 0)
+        return -1;
+    Registry &r = registry();
+    std::call_once(r.cache_once, load_cache);
+    return r.selected[K_pad / 32].load();
+}
+
+hp_status hp_autotune(const hp_structs *s, const void *d_ws, uint64_t seq_lo, uint64_t n_seq,
+                      int repeats, float *ms, int *best, void *stream)
+{
+    if (!s || !d_ws)
+        return fail(HP_EINVAL, "NULL structures or workspace");
+    if (n_seq == 0 || seq_lo + n_seq > (uint64_t(1) << s->N) || seq_lo + n_seq < seq_lo)
+        return fail(HP_EINVAL, "tuning range outside [0, 2^N)");
+    if (repeats < 1)
+        repeats = 1;
+    const int KB = int(s->K_pad / 32);
+    const auto &vars = registry().by_kb[KB];
+    if (vars.empty())
+        return fail(HP_EUNSUPPORTED, "no compiled tile shape for this K_pad");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess)
+        err = hipEventCreate(&e1);
+    int best_idx = -1;
+    float best_ms = 0.f;
+    for (size_t i = 0; i < vars.size() && err == hipSuccess; ++i) {
+        EnumJob j = make_enum_job(s, d_ws, seq_lo, seq_lo + n_seq, nullptr, nullptr, nullptr,
+                                  nullptr);
+        err = vars[i].launch(j, st);   // warm-up (code load, caches)
+        if (err != hipSuccess)
+            break;
+        err = hipEventRecord(e0, st);
+        for (int r = 0; r < repeats && err == hipSuccess; ++r)
+            err = vars[i].launch(j, st);
+        if (err == hipSuccess)
+            err = hipEventRecord(e1, st);
+        if (err == hipSuccess)
+            err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess)
+            err = hipEventElapsedTime(&t, e0, e1);
+        t /= float(repeats);
+        if (ms)
+            ms[i] = t;
+        if (err == hipSuccess && (best_idx < 0 || t < best_ms)) {
+            best_idx = int(i);
+            best_ms = t;
+        }
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (err != hipSuccess)
+        return fail(HP_EDEVICE, std::string("hp_autotune: ") + hipGetErrorString(err));
+    Registry &r = registry();
+    std::call_once(r.cache_once, load_cache);
+    r.selected[KB].store(best_idx);
+    store_cache(KB, vars[best_idx]);
+    if (best)
+        *best = best_idx;
+    return HP_OK;
+}
+
+}  // extern "C"

@@ -266,7 +266,7 @@ hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg)
         *msg = "box has no Hamiltonian path";
         return HP_EINVAL;
     }
-    if (n_conf > kMaxConf) {
+    if (n_conf >= kMaxConf) {
         *msg = "too many conformations";
         return HP_ERANGE;
     }
@@ -397,16 +397,28 @@ hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg)
             *msg = "internal: contact count differs from edges - bonds";
             return HP_EINVAL;
         }
-        // index rows: key low bits = position of c inside its window
-        uint32_t idx = c % kWindowConf;
-        a_byte(c, s->K) = static_cast<int8_t>(idx & 127);
-        a_byte(c, s->K + 1) = static_cast<int8_t>(-static_cast<int>(idx >> 7));
+        // index rows: key low bits = position of c inside its window, plus 1;
+        // padding columns keep all-zero rows, i.e. key 0 = "no conformation"
+        const uint32_t idx1 = c % kWindowConf + 1;
+        a_byte(c, s->K) = static_cast<int8_t>(idx1 & 127);
+        a_byte(c, s->K + 1) = static_cast<int8_t>(-static_cast<int>(idx1 >> 7));
     }
-    for (uint32_t c = n_conf; c < n_tiles * kTileConf; ++c)
-        a_byte(c, s->K) = static_cast<int8_t>(-1);   // padding columns: key -1, never a winner
 
-    s->pair_rows.assign(size_t(s->K_pad) * 2, 0xFF);
-    std::copy(s->pairs.begin(), s->pairs.end(), s->pair_rows.begin());
+    // B-operand row table, 4 bytes per row (i, j, c, 0): the kernels form the
+    // byte 0x80 * h_i h_j | c.  Rows beyond the pairs use monomer 63, which is
+    // always P, so only their constant c remains: 0x01 and 0x80 for the two
+    // index rows, 0 for padding.
+    s->pair_rows.assign(size_t(s->K_pad) * 4, 0);
+    for (uint32_t k = 0; k < s->K_pad; ++k) {
+        uint8_t *r = &s->pair_rows[size_t(k) * 4];
+        if (k < s->K) {
+            r[0] = s->pairs[2 * k];
+            r[1] = s->pairs[2 * k + 1];
+        } else {
+            r[0] = r[1] = 63;
+            r[2] = k == s->K ? 0x01 : (k == s->K + 1 ? 0x80 : 0x00);
+        }
+    }
 
     // ---- workspace layout ---------------------------------------------------
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
