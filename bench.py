@@ -36,6 +36,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every compiled tile shape first and use the fastest "
+                         "(default: the library's default shape, whose HBM counters are "
+                         "recorded under profiles/)")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiling run: no extras, no CPU baseline, plus a 256 MiB device "
+                         "copy used to calibrate the HBM byte counters")
     return ap.parse_args()
 
 
@@ -78,6 +85,15 @@ def main():
     ws = s.workspace()
     t_struct = time.time() - t0
     N, total, n_conf = s.N, 1 << s.N, s.n_conf
+    if args.profile:
+        args.no_extra = True
+        args.no_cpu_baseline = True
+    tune_ms = None
+    if args.autotune:
+        _, tune_ms = hp.hp_autotune(s, ws, 0, 1 << 20, repeats=2)
+    shape_idx = hp.hp_gemm_selected(s.K_pad)
+    T, NW, mode = hp.hp_gemm_shapes(s.K_pad)[shape_idx]
+    kname = "k_gemm<%d,%d,%d,%d>" % (s.K_pad // 32, T, NW, mode)
     pairs = total * n_conf
 
     out = torch.empty(total, dtype=torch.int16, device=dev)
@@ -150,6 +166,7 @@ def main():
                         "(int8-MFMA form) + single-mutation neighbour counts + union-find",
             "lattice": "3x3x3", "N": N, "sequences": total, "n_conf": n_conf,
             "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "form": "gemm_i8",
+            "tile_shape": {"T": T, "NW": NW, "mode": "lds" if mode == 0 else "direct"},
         },
         "roofline": {
             "bound": "mfma",
@@ -157,8 +174,8 @@ def main():
             "peak": PEAK_INT8_TOPS,
             "unit": "TOP/s",
             "frac": achieved_tops / PEAK_INT8_TOPS,
-            "traffic": None,
-            "kernel": "k_gemm<5,4,4> (hp_enumerate, int8 MFMA)",
+            "traffic": recorded_traffic(kname),
+            "kernel": kname + " (hp_enumerate, int8 MFMA)",
             "ops_per_unit": 2 * s.K,
         },
     }
@@ -171,13 +188,41 @@ def main():
         "top_class": top,
         "top_designability": int(d[top]),
         "structures_s": t_struct,
+        "autotune_ms_per_shape": tune_ms,
     }
     if not args.no_extra:
         extra.update(extra_measurements(hp, s, ws, dev))
+    if args.profile:
+        # a plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters
+        a = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        extra["calibration_copy_bytes"] = a.numel()
     result["extra"] = extra
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(dims, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def recorded_traffic(kname):
+    """HBM bytes per full-map launch of `kname`, from the calibrated
+    FETCH_SIZE / WRITE_SIZE counter summary in profiles/, or None when that
+    summary is for another kernel."""
+    path = os.path.join(ROOT, "profiles", "k_gemm_3x3x3_hbm_traffic.txt")
+    try:
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("kernel") != kname:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def extra_measurements(hp, s, ws, dev):
@@ -197,8 +242,10 @@ def extra_measurements(hp, s, ws, dev):
         res["3x3x3_slice_%s_evals_per_s" % name] = n * s.n_conf / (t.ms() * 1e-3)
     res["gemm_over_popcount_3x3x3"] = (res["3x3x3_slice_gemm_i8_evals_per_s"] /
                                        res["3x3x3_slice_popcount_evals_per_s"])
+    # the popcount loop issues 2W + 4 VALU instructions per pair (W ANDs, W
+    # bit counts, 4 for the key and top-2 update)
     res["popcount_valu_frac_3x3x3"] = (res["3x3x3_slice_popcount_evals_per_s"] *
-                                       (2 * s.W + 2.5) / (PEAK_VALU_TOPS * 1e12))
+                                       (2 * s.W + 4) / (PEAK_VALU_TOPS * 1e12))
     s6 = hp.Structures(6, 6, 1)
     ws6 = s6.workspace()
     n6 = 1 << 28

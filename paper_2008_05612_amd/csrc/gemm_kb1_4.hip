@@ -11,8 +11,8 @@ static const GemmVariant kVariants[] = {
     HP_GEMM_VARIANT(2, 4, 4, kLds),
     HP_GEMM_VARIANT(2, 2, 4, kDirect),
     HP_GEMM_VARIANT(3, 2, 4, kLds),
-    HP_GEMM_VARIANT(4, 2, 4, kLds),
     HP_GEMM_VARIANT(4, 4, 4, kLds),
+    HP_GEMM_VARIANT(4, 2, 4, kLds),
     HP_GEMM_VARIANT(4, 2, 4, kDirect),
 };
 

@@ -6,11 +6,11 @@
 namespace hpmap {
 
 static const GemmVariant kVariants[] = {
+    HP_GEMM_VARIANT(5, 2, 8, kLds),
     HP_GEMM_VARIANT(5, 2, 4, kLds),
     HP_GEMM_VARIANT(5, 2, 4, kDirect),
     HP_GEMM_VARIANT(5, 4, 4, kLds),
     HP_GEMM_VARIANT(5, 4, 4, kDirect),
-    HP_GEMM_VARIANT(5, 2, 8, kLds),
     HP_GEMM_VARIANT(5, 3, 4, kLds),
     HP_GEMM_VARIANT(5, 3, 4, kDirect),
     HP_GEMM_VARIANT(5, 1, 8, kDirect),

@@ -1,0 +1,156 @@
+"""Full genotype-phenotype map of one lattice, streamed in sequence blocks.
+
+    python -m paper_2008_05612_amd.fullmap --lattice 6x6 [--form gemm|popcount]
+        [--block-bits 30] [--neighbors] [--checkpoint FILE] [--json OUT]
+
+Every block of 2^block_bits sequences is one hp_enumerate launch; a progress
+line is printed per block.  The uint16 map stays resident on the device
+(2^36 x 2 B = 137 GB for 6x6) unless --no-map is given.  With --checkpoint,
+the accumulated designability is written after every block and a rerun
+resumes after the last finished block (the map of skipped blocks is then not
+available, so --neighbors is refused on a resumed run).
+
+All device work goes through the C ABI (hp_enumerate, hp_neighbors).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+from . import _binding as hp
+
+
+def _parse_lattice(text: str):
+    dims = [int(x) for x in text.lower().split("x")]
+    while len(dims) < 3:
+        dims.append(1)
+    return tuple(dims)
+
+
+def _load_checkpoint(path, dims, form, block_bits, n_class):
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ck = json.load(f)
+    if (tuple(ck["dims"]) != dims or ck["form"] != form or ck["block_bits"] != block_bits
+            or len(ck["designability"]) != n_class):
+        raise ValueError("checkpoint %s is for another run" % path)
+    return ck
+
+
+def _save_checkpoint(path, dims, form, block_bits, next_block, desig, nondesign):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump({"dims": list(dims), "form": form, "block_bits": block_bits,
+                   "next_block": next_block, "designability": [int(x) for x in desig],
+                   "nondesign": int(nondesign)}, f)
+    os.replace(tmp, path)
+
+
+def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=False,
+        checkpoint=None, progress=print, device="cuda"):
+    """Enumerate all 2^N sequences of the box; returns a summary dict (and the
+    device map under key "map" when keep_map)."""
+    import numpy as np
+    import torch
+
+    s = hp.Structures(*dims)
+    ws = s.workspace(device)
+    N = s.N
+    total = 1 << N
+    block = 1 << min(block_bits, N)
+    n_blocks = total // block
+    desig = torch.zeros(s.n_class, dtype=torch.int64, device=device)
+    nond = torch.zeros(1, dtype=torch.int64, device=device)
+    start_block = 0
+    ck = _load_checkpoint(checkpoint, dims, form, block_bits, s.n_class)
+    if ck:
+        start_block = ck["next_block"]
+        desig.copy_(torch.tensor(np.array(ck["designability"], dtype=np.uint64).view(np.int64)))
+        nond.fill_(ck["nondesign"])
+        if neighbors and start_block > 0:
+            raise ValueError("neighbour counts need the whole map; resume without --neighbors")
+        progress("resuming at block %d of %d" % (start_block, n_blocks))
+    out = torch.empty(total, dtype=torch.int16, device=device) if keep_map else None
+    t0 = time.time()
+    for b in range(start_block, n_blocks):
+        lo, hi = b * block, (b + 1) * block
+        tb = time.time()
+        hp.hp_enumerate(s, ws, form, lo, hi, out[lo:hi] if out is not None else None, None,
+                        desig, nond)
+        torch.cuda.synchronize()
+        if checkpoint:
+            _save_checkpoint(checkpoint, dims, form, block_bits, b + 1,
+                             desig.cpu().numpy().view(np.uint64), int(nond.item()))
+        progress("block %d/%d [%d, %d) %.2f s" % (b + 1, n_blocks, lo, hi, time.time() - tb))
+    wall = time.time() - t0
+    d = desig.cpu().numpy().view(np.uint64)
+    nd = int(nond.item())
+    summary = {
+        "lattice": "x".join(str(x) for x in dims if x > 1) or "1",
+        "N": N, "sequences": total, "n_conf": s.n_conf, "n_class": s.n_class,
+        "form": "gemm_i8" if form == hp.FORM_GEMM_I8 else "popcount",
+        "blocks": n_blocks, "block_sequences": block, "resumed_at_block": start_block,
+        "wall_s": wall, "evals_per_s": (n_blocks - start_block) * block * s.n_conf / wall,
+        "designing": int(d.sum()), "nondesign": nd,
+        "designable_classes": int((d > 0).sum()),
+        "top_class": int(d.argmax()), "top_designability": int(d.max()),
+        "designability_sha256": hashlib.sha256(d.astype("<u8").tobytes()).hexdigest(),
+        "sum_check": int(d.sum()) + nd == total,
+    }
+    if neighbors and out is not None:
+        z = lambda n: torch.zeros(n, dtype=torch.int64, device=device)  # noqa: E731
+        neu, dele, oth, row = z(s.n_class), z(s.n_class), z(s.n_class), z(s.n_class + 1)
+        tn = time.time()
+        hp.hp_neighbors(s, out, neu, dele, oth, summary["top_class"], row)
+        torch.cuda.synchronize()
+        summary["neighbors_s"] = time.time() - tn
+        neu_h = neu.cpu().numpy().view(np.uint64)
+        dele_h = dele.cpu().numpy().view(np.uint64)
+        oth_h = oth.cpu().numpy().view(np.uint64)
+        des = d > 0
+        summary["neighbor_sum_check"] = bool(np.array_equal(neu_h + dele_h + oth_h,
+                                                            np.uint64(N) * d))
+        rho = neu_h[des] / (N * d[des]).astype(np.float64)
+        null = d[des] / float(total)
+        summary["robust_above_null_fraction"] = float((rho > null).mean())
+        summary["mean_phi_del"] = float((dele_h[des] / (N * d[des]).astype(np.float64)).mean())
+        summary["isolated_phenotypes"] = int((oth_h[des] == 0).sum())
+        summary["phenotypes_connected_to_top"] = int((row[:s.n_class].cpu().numpy() > 0).sum())
+        summary["_counts"] = (neu_h, dele_h, oth_h)
+    summary["_designability"] = d
+    if out is not None:
+        summary["map"] = out
+    summary["_structs"] = s
+    return summary
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--lattice", default="6x6")
+    ap.add_argument("--form", choices=["gemm", "popcount"], default="gemm")
+    ap.add_argument("--block-bits", type=int, default=30)
+    ap.add_argument("--neighbors", action="store_true")
+    ap.add_argument("--no-map", action="store_true")
+    ap.add_argument("--checkpoint")
+    ap.add_argument("--json")
+    a = ap.parse_args(argv)
+    form = hp.FORM_GEMM_I8 if a.form == "gemm" else hp.FORM_POPCOUNT
+    res = run(_parse_lattice(a.lattice), form, a.block_bits, keep_map=not a.no_map,
+              neighbors=a.neighbors, checkpoint=a.checkpoint,
+              progress=lambda m: print(m, flush=True))
+    pub = {k: v for k, v in res.items() if not k.startswith("_") and k != "map"}
+    line = json.dumps(pub)
+    print(line, flush=True)
+    if a.json:
+        with open(a.json, "w") as f:
+            f.write(line + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
