@@ -75,7 +75,10 @@ typedef struct {
     uint32_t nbp;         /* non-bonded contacts of every compact structure */
     uint32_t K;           /* odd-separation pairs (i, j), j - i >= 3 */
     uint32_t W;           /* 32-bit words per contact bitmask, ceil(K/32) */
-    uint32_t K_pad;       /* depth of the int8 product: K + 2 index rows, rounded up to 32 */
+    uint32_t K_pad;       /* depth of the int8 product: K + unary rows + 2 index rows, to 32 */
+    int32_t table[4];     /* contact energies {E_PP, E_PH, E_HP, E_HH} (integers) */
+    uint32_t unary_rows;  /* N for a table with E_HP != E_PP, else 0 */
+    uint32_t cmax;        /* largest number of contacts of one monomer in any structure */
 } hp_info;
 
 /*
@@ -88,6 +91,18 @@ typedef struct {
  * HP_ERANGE if N > 36 or the class count does not fit below HP_NONE.
  */
 hp_status hp_structures(int X, int Y, int Z, hp_structs **out);
+
+/*
+ * hp_structures_energy -- as hp_structures, with the general two-letter
+ * contact energies of Eq. 1: table = {E_PP, E_PH, E_HP, E_HH}, integers (the
+ * paper's Table 1 scaled by 10 is {0, -10, -10, -23}); hp_structures is the
+ * table {0, 0, 0, -1}.  Energies reported by hp_enumerate are in the table's
+ * units.  The table must be symmetric (E_PH == E_HP) and attractive:
+ * E_HH - 2 E_HP + E_PP <= 0 and E_HP - E_PP <= 0, not both 0; its weights
+ * must fit the int8 product (HP_EUNSUPPORTED otherwise) and the largest
+ * energy range must stay below 2^14 units (HP_ERANGE).
+ */
+hp_status hp_structures_energy(int X, int Y, int Z, const int32_t table[4], hp_structs **out);
 void hp_structs_free(hp_structs *s);
 hp_status hp_structs_info(const hp_structs *s, hp_info *info);
 
@@ -119,7 +134,7 @@ hp_status hp_upload(const hp_structs *s, void *d_ws, size_t ws_bytes, void *stre
  * (Methods: minimum of Eq. 1 over all folds; a sequence with no unique
  * minimum does not fold).  seq_hi <= 2^N.
  *   d_out[s - seq_lo]   phenotype (class id) or HP_NONE; may be NULL.
- *   d_emin[s - seq_lo]  minimum energy (int32, <= 0); may be NULL.
+ *   d_emin[s - seq_lo]  minimum energy (int32, in the table's units); may be NULL.
  *   d_designability[q] += number of sequences in range with phenotype q
  *                         (n_class uint64 counters; may be NULL).
  *   d_nondesign[0]     += number of deleterious sequences (may be NULL).

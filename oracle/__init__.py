@@ -59,6 +59,9 @@ def lib():
             "or_contacts": (c_int, [c_int, c_int, c_int, u8p, u8p]),
             "or_all_contacts": (c_long, [c_int, c_int, c_int, u8p, c_long, i32p, u8p]),
             "or_energy": (c_int, [c_u64, c_int, u8p]),
+            "or_energy_table": (c_int, [c_u64, c_int, u8p, i32p]),
+            "or_ground_states_table": (None, [c_long, i32p, u8p, i32p, i32p, c_u64, c_u64, u16p,
+                                              i32p, u64p, u64p]),
             "or_ground_states": (None, [c_long, i32p, u8p, i32p, c_u64, c_u64, u16p, i32p,
                                         u64p, u64p]),
             "or_ground_states_brute": (None, [c_int, c_int, c_int, u8p, c_long, c_u64, c_u64,
@@ -197,10 +200,38 @@ class GroundStates:
     nondesign: int
 
 
-def ground_states(st: Structures, lo: int = 0, hi: int | None = None) -> GroundStates:
-    """Ground states of every sequence in [lo, hi) against all conformations."""
+# Table 1 of the paper (E_HH = -2.3, E_HP = E_PH = -1, E_PP = 0), scaled by 10,
+# as {E_PP, E_PH, E_HP, E_HH}.
+HP1996_X10 = (0, -10, -10, -23)
+PURE_HP = (0, 0, 0, -1)
+
+
+def energy_table(s: int, pairs, table) -> int:
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.uint8).reshape(-1, 2))
+    t = np.ascontiguousarray(np.asarray(table, dtype=np.int32))
+    return int(lib().or_energy_table(int(s), p.shape[0], _p(p, ctypes.c_uint8),
+                                     _p(t, ctypes.c_int32)))
+
+
+def ground_states(st: Structures, lo: int = 0, hi: int | None = None,
+                  table=None) -> GroundStates:
+    """Ground states of every sequence in [lo, hi) against all conformations;
+    `table` = {E_PP, E_PH, E_HP, E_HH} (integers) or None for pure HP."""
     if hi is None:
         hi = 1 << st.N
+    if table is not None:
+        n = hi - lo
+        out = np.zeros(max(n, 1), dtype=np.uint16)
+        emin = np.zeros(max(n, 1), dtype=np.int32)
+        desig = np.zeros(max(st.n_class, 1), dtype=np.uint64)
+        nond = np.zeros(1, dtype=np.uint64)
+        t = np.ascontiguousarray(np.asarray(table, dtype=np.int32))
+        lib().or_ground_states_table(st.n_conf, _p(st.ct_off, ctypes.c_int32),
+                                     _p(st.pairs, ctypes.c_uint8),
+                                     _p(st.conf_to_class, ctypes.c_int32), _p(t, ctypes.c_int32),
+                                     lo, hi, _p(out, ctypes.c_uint16), _p(emin, ctypes.c_int32),
+                                     _p(desig, ctypes.c_uint64), _p(nond, ctypes.c_uint64))
+        return GroundStates(out[:n], emin[:n], desig[:st.n_class], int(nond[0]))
     n = hi - lo
     out = np.zeros(max(n, 1), dtype=np.uint16)
     emin = np.zeros(max(n, 1), dtype=np.int32)

@@ -451,6 +451,59 @@ int or_energy(uint64_t s, int ncontacts, const uint8_t *pairs)
     return e;
 }
 
+/* Eq. 1 with a general two-letter contact table: each contact (i,j) adds
+ * table[2*h_i + h_j]  (table = {E_PP, E_PH, E_HP, E_HH}, integers, e.g. the
+ * paper's Table 1 scaled by 10: {0, -10, -10, -23}).                       */
+int or_energy_table(uint64_t s, int ncontacts, const uint8_t *pairs, const int32_t *table)
+{
+    int e = 0;
+    for (int k = 0; k < ncontacts; k++)
+        e += table[2 * monomer(s, pairs[2 * k]) + monomer(s, pairs[2 * k + 1])];
+    return e;
+}
+
+/* Ground states with a contact table (see or_energy_table); otherwise as
+ * or_ground_states below.                                                   */
+void or_ground_states_table(long n_conf, const int32_t *ct_off, const uint8_t *pairs,
+                            const int32_t *conf_to_class, const int32_t *table,
+                            uint64_t lo, uint64_t hi, uint16_t *out, int32_t *emin,
+                            uint64_t *designability, uint64_t *nondesign)
+{
+    long count = (long)(hi - lo);
+    uint16_t *res = out ? out : (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(count > 0 ? count : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long t = 0; t < count; t++) {
+        uint64_t s = lo + (uint64_t)t;
+        int best = 0;
+        long nbest = 0;
+        long arg = -1;
+        for (long c = 0; c < n_conf; c++) {
+            int e = or_energy_table(s, ct_off[c + 1] - ct_off[c], pairs + 2 * (size_t)ct_off[c],
+                                    table);
+            if (nbest == 0 || e < best) {
+                best = e;
+                nbest = 1;
+                arg = c;
+            } else if (e == best) {
+                nbest++;
+            }
+        }
+        if (emin)
+            emin[t] = best;
+        res[t] = (nbest == 1) ? (uint16_t)conf_to_class[arg] : (uint16_t)OR_NONE;
+    }
+    for (long t = 0; t < count; t++) {
+        if (res[t] == OR_NONE) {
+            if (nondesign)
+                (*nondesign)++;
+        } else if (designability) {
+            designability[res[t]]++;
+        }
+    }
+    if (!out)
+        free(res);
+}
+
 /* Ground states for every sequence s in [lo, hi):
  *   emin[s-lo] = min over conformations of E(s,c);
  *   out[s-lo]  = class of the unique minimising conformation, or 0xFFFF when

@@ -40,7 +40,8 @@ class _Info(ctypes.Structure):
                 ("n_walks", ctypes.c_uint64), ("n_conf", ctypes.c_uint32),
                 ("n_class", ctypes.c_uint32), ("n_selfrev", ctypes.c_uint32),
                 ("nbp", ctypes.c_uint32), ("K", ctypes.c_uint32), ("W", ctypes.c_uint32),
-                ("K_pad", ctypes.c_uint32)]
+                ("K_pad", ctypes.c_uint32), ("table", ctypes.c_int32 * 4),
+                ("unary_rows", ctypes.c_uint32), ("cmax", ctypes.c_uint32)]
 
 
 class _Job(ctypes.Structure):
@@ -69,6 +70,8 @@ def library():
     st = ctypes.c_int
     sigs = {
         "hp_structures": (st, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]),
+        "hp_structures_energy": (st, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(vp)]),
         "hp_structs_free": (None, [vp]),
         "hp_structs_info": (st, [vp, ctypes.POINTER(_Info)]),
         "hp_structs_export": (st, [vp, vp, vp, vp, vp, vp, vp]),
@@ -146,14 +149,20 @@ def _ptr(t, dtype=None, numel: Optional[int] = None, name: str = "buffer"):
 class Structures:
     """Owning wrapper of an hp_structs handle (host-side tables)."""
 
-    def __init__(self, X: int, Y: int, Z: int = 1):
+    def __init__(self, X: int, Y: int, Z: int = 1, table=None):
         h = ctypes.c_void_p()
-        _check(library().hp_structures(X, Y, Z, ctypes.byref(h)), "hp_structures")
+        if table is None:
+            _check(library().hp_structures(X, Y, Z, ctypes.byref(h)), "hp_structures")
+        else:
+            t = (ctypes.c_int32 * 4)(*[int(x) for x in table])
+            _check(library().hp_structures_energy(X, Y, Z, t, ctypes.byref(h)),
+                   "hp_structures_energy")
         self._h = h
         info = _Info()
         _check(library().hp_structs_info(h, ctypes.byref(info)), "hp_structs_info")
         for name, _ in _Info._fields_:
-            setattr(self, name, int(getattr(info, name)))
+            v = getattr(info, name)
+            setattr(self, name, tuple(v) if name == "table" else int(v))
         self.dims = (X, Y, Z)
         self._ws = None
 
@@ -195,8 +204,10 @@ class Structures:
         return self._ws
 
 
-def hp_structures(X: int, Y: int, Z: int = 1) -> Structures:
-    return Structures(X, Y, Z)
+def hp_structures(X: int, Y: int, Z: int = 1, table=None) -> Structures:
+    """Structures of the X*Y*Z box; `table` = {E_PP, E_PH, E_HP, E_HH} or None
+    for pure HP (hp_structures_energy / hp_structures)."""
+    return Structures(X, Y, Z, table)
 
 
 def hp_workspace_bytes(s: Structures) -> int:

@@ -109,6 +109,15 @@ EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
     j.KB = int32_t(s->K_pad / 32);
     j.n_conf = int32_t(s->n_conf);
     j.n_tiles = int32_t((s->n_conf + kTileConf - 1) / kTileConf);
+    j.U = int32_t(s->U);
+    j.win_tiles = int32_t(s->win_tiles);
+    j.win_shift = int32_t(s->win_shift);
+    j.A = s->A;
+    j.B = s->B;
+    j.e0 = s->e0;
+    j.planes = int32_t(s->planes);
+    j.uw = int32_t(s->uw);
+    j.MW = int32_t(s->MW);
     return j;
 }
 
@@ -135,16 +144,24 @@ const char *hp_version(void) { return "hpmap 0.1 (gfx950)"; }
 
 hp_status hp_structures(int X, int Y, int Z, hp_structs **out)
 {
+    static const int32_t pure_hp[4] = {0, 0, 0, -1};
+    return hp_structures_energy(X, Y, Z, pure_hp, out);
+}
+
+hp_status hp_structures_energy(int X, int Y, int Z, const int32_t table[4], hp_structs **out)
+{
     if (!out)
         return fail(HP_EINVAL, "out pointer is NULL");
     *out = nullptr;
+    if (!table)
+        return fail(HP_EINVAL, "energy table is NULL");
     hp_structs *s = new (std::nothrow) hp_structs();
     if (!s)
         return fail(HP_ENOMEM, "out of host memory");
     std::string msg;
     hp_status st;
     try {
-        st = build_structures(X, Y, Z, s, &msg);
+        st = build_structures(X, Y, Z, table, s, &msg);
     } catch (const std::bad_alloc &) {
         st = HP_ENOMEM;
         msg = "out of host memory";
@@ -176,6 +193,10 @@ hp_status hp_structs_info(const hp_structs *s, hp_info *info)
     info->K = s->K;
     info->W = s->W;
     info->K_pad = s->K_pad;
+    for (int q = 0; q < 4; ++q)
+        info->table[q] = s->table[q];
+    info->unary_rows = s->U;
+    info->cmax = s->cmax;
     return HP_OK;
 }
 

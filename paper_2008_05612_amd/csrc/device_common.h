@@ -22,8 +22,6 @@ namespace hpmap {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kWinShift = 14;   // window key of the int8 form = (n << 14) | idx
-
 // Median of three, written as max(min(a, b), min(max(a, b), c)), which the
 // backend selects as one v_med3_i32.  No inline assembly here: the compiler
 // must see the instruction to insert the wait states between an MFMA and the
@@ -58,16 +56,18 @@ __device__ __forceinline__ void top2_merge(int &b, int &s, int b2, int s2)
     b = max(b, b2);
 }
 
-// Window key -> global key (0 stays 0): (k & 16383) is the position + 1.
-__device__ __forceinline__ int window_to_global(int k, int conf_base)
+// Window key S F + u (S = 2^win_shift, u = position + 1) -> global key
+// (F << 17) | (conformation + 1); 0 stays 0.
+__device__ __forceinline__ int window_to_global(int k, int conf_base, int win_shift)
 {
-    const int g = ((k >> kWinShift) << kKeyConfBits) | (conf_base + (k & ((1 << kWinShift) - 1)));
+    const int g = ((k >> win_shift) << kKeyConfBits) | (conf_base + (k & ((1 << win_shift) - 1)));
     return k == 0 ? 0 : g;
 }
 
-// Final decision for one sequence and the per-sequence outputs.
+// Final decision for one sequence and the per-sequence outputs.  The keys'
+// high part times fmul is F, and the minimum energy is e0 - F.
 __device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, bool valid, int gb,
-                                                int gs, bool count_lane)
+                                                int gs, bool count_lane, int fmul)
 {
     const int nb = gb >> kKeyConfBits;
     const int ns = gs >> kKeyConfBits;
@@ -79,7 +79,7 @@ __device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, bo
         if (j.out)
             j.out[s - j.lo] = q;
         if (j.emin)
-            j.emin[s - j.lo] = -nb;
+            j.emin[s - j.lo] = j.e0 - fmul * nb;
         if (uniq && j.desig)
             atomicAdd(&j.desig[q], 1ull);
     }
@@ -91,13 +91,13 @@ __device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, bo
 // B-operand fragments of one lane for T sequences: bytes of product rows
 // kbase .. kbase+15 with kbase = 32 kb + 16 half (byte q of a fragment is row
 // kbase + q).  Row k < K is the pair (i, i + d) of the k-th odd separation
-// d >= 3 in (d, i) order, and its byte is 0x80 * h_i h_{i+d}; row K is the
-// constant 0x01 and row K+1 the constant 0x80 (the index rows); rows beyond
-// are 0.  The pair of the first row is found by walking the run lengths
-// N - d; consecutive rows then advance (d, i) incrementally, so no table is
-// read.
+// d >= 3 in (d, i) order, and its byte is 0x80 * h_i h_{i+d}; rows K .. K+U-1
+// are the unary rows 0x80 * h_{k-K}; row K+U is the constant 0x01 and row
+// K+U+1 the constant 0x80 (the index rows); rows beyond are 0.  The pair of
+// the first row is found by walking the run lengths N - d; consecutive rows
+// then advance (d, i) incrementally, so no table is read.
 template <int KB, int T>
-__device__ __forceinline__ void p_fragments(const uint64_t (&s)[T], int half, int N, int K,
+__device__ __forceinline__ void p_fragments(const uint64_t (&s)[T], int half, int N, int K, int U,
                                             v4i (&pf)[T][KB])
 {
 #pragma unroll
@@ -117,11 +117,17 @@ __device__ __forceinline__ void p_fragments(const uint64_t (&s)[T], int half, in
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
                 const int k = kbase + 4 * q + bb;
-                const uint32_t c = k == K ? 0x01u : (k == K + 1 ? 0x80u : 0u);
-                const bool real = k < K;
+                const int ki = K + U;
+                const uint32_t c = k == ki ? 0x01u : (k == ki + 1 ? 0x80u : 0u);
+                const bool pair = k < K;
+                const bool unary = k >= K && k < ki;
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
-                    const uint32_t bit = real ? uint32_t((s[t] >> i) & (s[t] >> (i + d)) & 1u) : 0u;
+                    uint32_t bit = 0;
+                    if (pair)
+                        bit = uint32_t((s[t] >> i) & (s[t] >> (i + d)) & 1u);
+                    else if (unary)
+                        bit = uint32_t((s[t] >> (k - K)) & 1u);
                     w[t][q] |= ((bit << 7) | c) << (8 * bb);
                 }
                 ++i;                       // next row: next i, or the next run

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_batch(BatchHeader *hdr)
             gemm_body<kb, T, NW, MODE>(j, seq0, lds);         \
         break;
             HP_CASE(1) HP_CASE(2) HP_CASE(3) HP_CASE(4) HP_CASE(5)
-            HP_CASE(6) HP_CASE(7) HP_CASE(8) HP_CASE(9) HP_CASE(10)
+            HP_CASE(6) HP_CASE(7) HP_CASE(8) HP_CASE(9) HP_CASE(10) HP_CASE(11) HP_CASE(12)
 #undef HP_CASE
         default:
             break;
@@ -73,7 +73,7 @@ hipError_t launch_gemm_batch(void *d_batch_ws, int kb_max, int n_items, hipStrea
     if (kb_max <= 5)
         hipLaunchKernelGGL((k_gemm_batch<5, 2, 4, kLds>), dim3(grid), dim3(256), 0, st, hdr);
     else
-        hipLaunchKernelGGL((k_gemm_batch<10, 2, 4, kLds>), dim3(grid), dim3(256), 0, st, hdr);
+        hipLaunchKernelGGL((k_gemm_batch<12, 2, 4, kLds>), dim3(grid), dim3(256), 0, st, hdr);
     return hipGetLastError();
 }
 

@@ -10,27 +10,33 @@
 // Operands of v_mfma_i32_32x32x32_i8: A = C^T, 32 conformations x 32 rows per
 // block, stored pre-swizzled so that lane l's 16 bytes are one load; B = P for
 // 32 sequences, generated in registers once per sequence tile and held for
-// the whole sweep over conformations.  Entries are -128 on both sides, so each
-// H-H contact adds 16384.  Rows K and K+1 carry u = 1 + the conformation's
-// position within its window of 16352 conformations (P = 1, C = u & 127 and
-// P = -128, C = -(u >> 7)), so the accumulator IS the window key
-// 16384 n + u and the epilogue needs no index arithmetic: per two values one
-// med3, one max3 and half of a max3.  Padding columns hold key 0.
+// the whole sweep over conformations.  For pure HP the entries are -128 on
+// both sides, so each H-H contact adds S = 16384.  A general two-letter table
+// maximises F = A n + B sum_i h_i c_i: pair rows carry C = -A m, N more
+// "unary" rows carry P = -128 h_i and C = -B c_i m, so the product is S F with
+// S = 128 m.  The two rows after them carry u = 1 + the conformation's
+// position within its key window (P = 1, C = u & 127 and P = -128,
+// C = -(u >> 7)), so the accumulator IS the window key S F + u and the
+// epilogue needs no index arithmetic: per two values one med3, one max3 and
+// half of a max3.  Padding columns hold key 0.
 //
-// Two staging modes for A:
+// Three staging modes for A:
 //   kLds    : the workgroup copies each conformation tile global -> LDS
 //             (double-buffered, one barrier per tile) and every wave reads its
 //             fragments from LDS;
 //   kDirect : every wave loads its fragments straight from global memory
 //             (L1/L2-resident, all waves sweep the same tiles) into registers,
-//             one tile ahead; no LDS, no barriers.
+//             one tile ahead; no LDS, no barriers;
+//   kPipe   : as kLds, but software-pipelined: the MFMAs of tile t+1 are
+//             issued before the epilogue of tile t, into a second set of
+//             accumulators, so one wave's matrix and vector work overlap.
 #pragma once
 
 #include "device_common.h"
 
 namespace hpmap {
 
-enum { kLds = 0, kDirect = 1 };
+enum { kLds = 0, kDirect = 1, kPipe = 2 };
 
 template <int KB, int NW>
 struct TileStage {
@@ -84,12 +90,12 @@ __device__ __forceinline__ void epilogue_tile(const v16i (&acc)[T], int (&b)[T],
 
 template <int T>
 __device__ __forceinline__ void fold_window(int (&b)[T], int (&sc)[T], int (&gb)[T], int (&gs)[T],
-                                            int conf_base)
+                                            int conf_base, int win_shift)
 {
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        top2_merge(gb[t], gs[t], window_to_global(b[t], conf_base),
-                   window_to_global(sc[t], conf_base));
+        top2_merge(gb[t], gs[t], window_to_global(b[t], conf_base, win_shift),
+                   window_to_global(sc[t], conf_base, win_shift));
         b[t] = sc[t] = 0;
     }
 }
@@ -112,7 +118,7 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
 #pragma unroll
         for (int t = 0; t < T; ++t)
             seqs[t] = seq0 + t * 32 + col;
-        p_fragments<KB, T>(seqs, half, j.N, j.K, pf);
+        p_fragments<KB, T>(seqs, half, j.N, j.K, j.U, pf);
     }
 
     int b[T], sc[T], gb[T], gs[T];
@@ -121,7 +127,9 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
         b[t] = sc[t] = gb[t] = gs[t] = 0;
 
     const int n_tiles = j.n_tiles;
-    int wend = min(kWindowTiles, n_tiles);
+    const int win_tiles = j.win_tiles;
+    const int win_shift = j.win_shift;
+    int wend = min(win_tiles, n_tiles);
     int conf_base = 0;
 
     if constexpr (MODE == kLds) {
@@ -142,12 +150,80 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
             mma_tile<KB, T>(a, pf, acc);
             epilogue_tile<T>(acc, b, sc);
             if (tile + 1 == wend) {
-                fold_window<T>(b, sc, gb, gs, conf_base);
-                conf_base += kWindowConf;
-                wend = min(wend + kWindowTiles, n_tiles);
+                fold_window<T>(b, sc, gb, gs, conf_base, win_shift);
+                conf_base += win_tiles * kTileConf;
+                wend = min(wend + win_tiles, n_tiles);
             }
             if (more)
                 stg.store(lds + ((tile + 1) & 1) * (KB * 64));
+            __syncthreads();
+        }
+    } else if constexpr (MODE == kPipe) {
+        // Double-buffered LDS; half-step t: prefetch tile t+2 from global,
+        // MFMAs of tile t+1 (buffer (t+1)&1), epilogue of tile t, store tile
+        // t+2 into buffer t&1 (last read by the MFMAs of tile t, before the
+        // previous barrier), barrier.  Unrolled by two so the accumulator
+        // sets alternate without copies.
+        constexpr int TV = KB * 64;
+        TileStage<KB, NW> stg;
+        stg.load(A, 0);
+        stg.store(lds);
+        if (n_tiles > 1) {
+            stg.load(A, 1);
+            stg.store(lds + TV);
+        }
+        __syncthreads();
+        v16i acc0[T], acc1[T];
+        {
+            v4i a[KB];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                a[kb] = lds[kb * 64 + lane];
+            mma_tile<KB, T>(a, pf, acc0);
+        }
+        for (int tile = 0; tile < n_tiles; tile += 2) {
+            const bool has1 = tile + 1 < n_tiles;
+            const bool has2 = tile + 2 < n_tiles;
+            const bool has3 = tile + 3 < n_tiles;
+            const v4i *buf0 = lds + (tile & 1) * TV;         // holds tile (then tile+2)
+            const v4i *buf1 = lds + ((tile + 1) & 1) * TV;   // holds tile+1 (then tile+3)
+            if (has2)
+                stg.load(A, tile + 2);
+            if (has1) {
+                v4i a[KB];
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    a[kb] = buf1[kb * 64 + lane];
+                mma_tile<KB, T>(a, pf, acc1);
+            }
+            epilogue_tile<T>(acc0, b, sc);
+            if (tile + 1 == wend) {
+                fold_window<T>(b, sc, gb, gs, conf_base, win_shift);
+                conf_base += win_tiles * kTileConf;
+                wend = min(wend + win_tiles, n_tiles);
+            }
+            if (has2)
+                stg.store(lds + (tile & 1) * TV);
+            __syncthreads();
+            if (!has1)
+                break;
+            if (has3)
+                stg.load(A, tile + 3);
+            if (has2) {
+                v4i a[KB];
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    a[kb] = buf0[kb * 64 + lane];
+                mma_tile<KB, T>(a, pf, acc0);
+            }
+            epilogue_tile<T>(acc1, b, sc);
+            if (tile + 2 == wend) {
+                fold_window<T>(b, sc, gb, gs, conf_base, win_shift);
+                conf_base += win_tiles * kTileConf;
+                wend = min(wend + win_tiles, n_tiles);
+            }
+            if (has3)
+                stg.store(lds + ((tile + 1) & 1) * TV);
             __syncthreads();
         }
     } else {
@@ -166,9 +242,9 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
             mma_tile<KB, T>(a, pf, acc);
             epilogue_tile<T>(acc, b, sc);
             if (tile + 1 == wend) {
-                fold_window<T>(b, sc, gb, gs, conf_base);
-                conf_base += kWindowConf;
-                wend = min(wend + kWindowTiles, n_tiles);
+                fold_window<T>(b, sc, gb, gs, conf_base, win_shift);
+                conf_base += win_tiles * kTileConf;
+                wend = min(wend + win_tiles, n_tiles);
             }
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb)
@@ -182,14 +258,14 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
         const int os = __shfl_xor(gs[t], 32);
         top2_merge(gb[t], gs[t], ob, os);
         const uint64_t s = seq0 + t * 32 + col;
-        finish_sequence(j, s, half == 0 && s < j.hi, gb[t], gs[t], lane == 0);
+        finish_sequence(j, s, half == 0 && s < j.hi, gb[t], gs[t], lane == 0, 1);
     }
 }
 
 template <int KB, int T, int NW, int MODE>
 __global__ __launch_bounds__(NW * 64) void k_gemm(EnumJob j)
 {
-    __shared__ v4i lds[MODE == kLds ? 2 * KB * 64 : 1];
+    __shared__ v4i lds[MODE == kDirect ? 1 : 2 * KB * 64];
     const uint64_t seq0 = j.lo + uint64_t(blockIdx.x) * (NW * T * 32);
     gemm_body<KB, T, NW, MODE>(j, seq0, lds);
 }

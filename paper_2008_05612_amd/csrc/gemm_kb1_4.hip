@@ -14,6 +14,9 @@ static const GemmVariant kVariants[] = {
     HP_GEMM_VARIANT(4, 4, 4, kLds),
     HP_GEMM_VARIANT(4, 2, 4, kLds),
     HP_GEMM_VARIANT(4, 2, 4, kDirect),
+    HP_GEMM_VARIANT(4, 2, 8, kPipe),
+    HP_GEMM_VARIANT(4, 4, 4, kPipe),
+    HP_GEMM_VARIANT(2, 2, 4, kPipe),
 };
 
 int gemm_variants_kb1_4(const GemmVariant **out)

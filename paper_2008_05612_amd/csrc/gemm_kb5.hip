@@ -14,6 +14,10 @@ static const GemmVariant kVariants[] = {
     HP_GEMM_VARIANT(5, 3, 4, kLds),
     HP_GEMM_VARIANT(5, 3, 4, kDirect),
     HP_GEMM_VARIANT(5, 1, 8, kDirect),
+    HP_GEMM_VARIANT(5, 2, 8, kPipe),
+    HP_GEMM_VARIANT(5, 2, 4, kPipe),
+    HP_GEMM_VARIANT(5, 4, 4, kPipe),
+    HP_GEMM_VARIANT(5, 3, 4, kPipe),
 };
 
 int gemm_variants_kb5(const GemmVariant **out)

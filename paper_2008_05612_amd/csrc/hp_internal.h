@@ -14,19 +14,20 @@ namespace hpmap {
 constexpr int kMaxN = 36;            // sequences are 64-bit, ids 16-bit
 constexpr int kTileConf = 32;        // conformations per MFMA tile (rows of A)
 // Keys of the running minimum search are non-negative; 0 means "no
-// conformation".  Global key = (n_HH << 17) | (conformation + 1); window key of
-// the int8 form = (n_HH << 14) | (position in window + 1), with windows of 511
-// tiles so that position + 1 stays below 2^14.
-constexpr int kWindowTiles = 511;
-constexpr int kWindowConf = kWindowTiles * kTileConf;   // 16352
+// conformation".  F is the quantity maximised (F = A n_HH + B sum_i h_i c_i,
+// the negated energy up to a constant; F = n_HH for pure HP).  Global key =
+// (F << 17) | (conformation + 1); window key of the int8 form =
+// S F + (position in window + 1) with S = 2^win_shift, windows being the
+// largest whole number of 32-conformation tiles below S.
 constexpr int kKeyConfBits = 17;
 constexpr uint32_t kMaxConf = (1u << kKeyConfBits) - 1;
+constexpr int kMaxKB = 12;              // product depth K_pad <= 384
 
 // Byte offsets of the packed tables inside the device workspace.
 struct WsLayout {
     size_t c2q = 0;      // uint16_t[n_conf]
     size_t pairs = 0;    // uint8_t[K_pad][4] row table (i, j, constant, 0)
-    size_t masks = 0;    // uint32_t[n_conf][W]
+    size_t masks = 0;    // uint32_t[n_conf][MW]: W pair words, then unary bit planes
     size_t gemm_a = 0;   // int8_t[n_tiles][K_pad/32][64 lanes][16]
     size_t total = 0;
 };
@@ -38,6 +39,14 @@ struct hp_structs {
     uint32_t G = 0;
     uint64_t n_walks = 0;
     uint32_t n_conf = 0, n_class = 0, n_selfrev = 0, nbp = 0, K = 0, W = 0, K_pad = 0;
+    // energy model: table {E_PP, E_PH, E_HP, E_HH}; maximised F = A n + B u
+    int32_t table[4] = {0, 0, 0, -1};
+    int32_t A = 1, B = 0, e0 = 0;     // E = e0 - F, e0 = E_PP * nbp
+    uint32_t U = 0;                   // unary rows (N when B != 0)
+    uint32_t cmax = 0;                // largest contact count of one monomer
+    uint32_t planes = 0, uw = 0;      // bit planes of c_i and 32-bit words per plane
+    uint32_t MW = 0;                  // mask words per conformation: W + planes * uw
+    uint32_t win_shift = 14, win_tiles = 511;
     std::vector<uint8_t> walks;       // n_conf * N canonical site sequences, ascending
     std::vector<uint16_t> c2q;        // conformation -> class
     std::vector<uint32_t> rev_conf;   // conformation of the reversed chain
@@ -53,7 +62,8 @@ struct hp_structs {
 namespace hpmap {
 
 // Host enumeration (structures.cpp).  Returns HP_OK or an error with msg set.
-hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg);
+hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_structs *s,
+                           std::string *msg);
 
 struct EnumJob;
 // Kernel-side descriptor of one enumeration over [lo, hi) (capi.cpp).

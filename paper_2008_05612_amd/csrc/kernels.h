@@ -19,8 +19,12 @@ struct EnumJob {
     unsigned long long *desig;      // designability, += (or null)
     unsigned long long *nondesign;  // deleterious count, += (or null)
     uint64_t lo, hi;                // sequence range [lo, hi)
-    int32_t N, K, W, KB;            // chain length, pairs, mask words, K_pad/32
+    int32_t N, K, W, KB;            // chain length, pairs, pair-mask words, K_pad/32
     int32_t n_conf, n_tiles;        // conformations, 32-conformation tiles
+    int32_t U;                      // unary product rows (0 for pure HP)
+    int32_t win_tiles, win_shift;   // int8-form key windows
+    int32_t A, B, e0;               // F = A n + B u, E = e0 - F
+    int32_t planes, uw, MW;         // popcount form: unary bit planes, words, mask stride
 };
 
 // Work list of a batched launch, laid out in the batch workspace.
@@ -43,6 +47,7 @@ struct GemmVariant {
 int gemm_variants_kb1_4(const GemmVariant **out);
 int gemm_variants_kb5(const GemmVariant **out);
 int gemm_variants_kb6_10(const GemmVariant **out);
+int gemm_variants_kb11_12(const GemmVariant **out);
 
 // Shape used for product depth KB (process-wide choice; default: first listed).
 const GemmVariant *gemm_selected_variant(int KB);

@@ -22,8 +22,6 @@ namespace hpmap {
 
 namespace {
 
-constexpr int kMaxKB = 10;
-
 struct Registry {
     std::vector<GemmVariant> by_kb[kMaxKB + 1];
     std::atomic<int> selected[kMaxKB + 1];
@@ -34,7 +32,7 @@ struct Registry {
         for (auto &s : selected)
             s.store(0);
         int (*groups[])(const GemmVariant **) = {gemm_variants_kb1_4, gemm_variants_kb5,
-                                                 gemm_variants_kb6_10};
+                                                 gemm_variants_kb6_10, gemm_variants_kb11_12};
         for (auto g : groups) {
             const GemmVariant *v = nullptr;
             int n = g(&v);

@@ -209,7 +209,8 @@ void canonicalise(const Box &b, const uint8_t *walk, uint8_t *out)
 
 }  // namespace
 
-hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg)
+hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_structs *s,
+                           std::string *msg)
 {
     if (X < 1 || Y < 1 || Z < 1) {
         *msg = "box dimensions must be >= 1";
@@ -341,22 +342,13 @@ hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg)
         }
     s->K = static_cast<uint32_t>(s->pairs.size() / 2);
     s->W = std::max<uint32_t>(1, (s->K + 31) / 32);
-    s->K_pad = ((s->K + 2 + 31) / 32) * 32;
 
-    // ---- contacts, bitmasks, int8 contact matrix -------------------------
+    // ---- contacts and per-monomer contact counts -------------------------
     const int edges = (X - 1) * Y * Z + X * (Y - 1) * Z + X * Y * (Z - 1);
     s->nbp = static_cast<uint32_t>(edges - (N - 1));
     s->contacts.assign(size_t(n_conf) * s->nbp * 2, 0);
-    s->masks.assign(size_t(n_conf) * s->W, 0);
-    const uint32_t KB = s->K_pad / 32;
-    const uint32_t n_tiles = (n_conf + kTileConf - 1) / kTileConf;
-    s->gemm_a.assign(size_t(n_tiles) * KB * 1024, 0);
-    auto a_byte = [&](uint32_t c, uint32_t k) -> int8_t & {
-        uint32_t t = c / kTileConf, col = c % kTileConf;
-        uint32_t kb = k / 32, kk = k % 32;
-        uint32_t lane = col + 32 * (kk / 16);
-        return s->gemm_a[((size_t(t) * KB + kb) * 64 + lane) * 16 + kk % 16];
-    };
+    std::vector<uint8_t> deg(size_t(n_conf) * N, 0);
+    uint32_t cmax = 0;
     for (uint32_t c = 0; c < n_conf; ++c) {
         const uint8_t *w = &s->walks[size_t(c) * N];
         int pos[kMaxN];
@@ -381,43 +373,119 @@ hp_status build_structures(int X, int Y, int Z, hp_structs *s, std::string *msg)
                     *msg = "internal: contact count exceeds edges - bonds";
                     return HP_EINVAL;
                 }
-                s->contacts[(size_t(c) * s->nbp + nc) * 2] = static_cast<uint8_t>(i);
-                s->contacts[(size_t(c) * s->nbp + nc) * 2 + 1] = static_cast<uint8_t>(j);
-                ++nc;
-                int k = pidx[size_t(i) * N + j];
-                if (k < 0) {
+                if (pidx[size_t(i) * N + j] < 0) {
                     *msg = "internal: contact with even separation";
                     return HP_EINVAL;
                 }
-                s->masks[size_t(c) * s->W + k / 32] |= 1u << (k % 32);
-                a_byte(c, k) = static_cast<int8_t>(-128);
+                s->contacts[(size_t(c) * s->nbp + nc) * 2] = static_cast<uint8_t>(i);
+                s->contacts[(size_t(c) * s->nbp + nc) * 2 + 1] = static_cast<uint8_t>(j);
+                ++nc;
+                ++deg[size_t(c) * N + i];
+                ++deg[size_t(c) * N + j];
             }
         }
         if (nc != s->nbp) {
             *msg = "internal: contact count differs from edges - bonds";
             return HP_EINVAL;
         }
+        for (int i = 0; i < N; ++i)
+            cmax = std::max<uint32_t>(cmax, deg[size_t(c) * N + i]);
+    }
+    s->cmax = cmax;
+
+    // ---- energy model ------------------------------------------------------
+    // Eq. 1 with a symmetric two-letter table sums, over contacts (i, j),
+    // E_PP + (E_HP - E_PP)(h_i + h_j) + (E_HH - 2 E_HP + E_PP) h_i h_j, so
+    // E = e0 - F with F = A n_HH + B sum_i h_i c_i, e0 = E_PP nbp,
+    // A = -(E_HH - 2 E_HP + E_PP), B = -(E_HP - E_PP).
+    for (int q = 0; q < 4; ++q)
+        s->table[q] = table[q];
+    if (table[1] != table[2]) {
+        *msg = "contact table must be symmetric (E_PH == E_HP)";
+        return HP_EINVAL;
+    }
+    const int64_t A = -(int64_t(table[3]) - 2 * int64_t(table[2]) + table[0]);
+    const int64_t B = -(int64_t(table[2]) - table[0]);
+    if (A < 0 || B < 0 || (A == 0 && B == 0)) {
+        *msg = "only attractive tables are handled: need E_HH - 2 E_HP + E_PP <= 0 and "
+               "E_HP - E_PP <= 0, not both zero";
+        return HP_EUNSUPPORTED;
+    }
+    // int8 scale m: the largest power of two with A m <= 128 and B cmax m <= 128
+    int m = 128;
+    while (m >= 1 && (A * m > 128 || B * int64_t(cmax) * m > 128))
+        m /= 2;
+    if (m < 1) {
+        *msg = "contact table too large for the int8 product";
+        return HP_EUNSUPPORTED;
+    }
+    const int64_t fmax = A * s->nbp + 2 * B * s->nbp;
+    if (fmax >= (int64_t(1) << 14)) {
+        *msg = "contact table too large for 32-bit search keys";
+        return HP_ERANGE;
+    }
+    s->A = int32_t(A);
+    s->B = int32_t(B);
+    s->e0 = table[0] * int32_t(s->nbp);
+    s->U = B ? uint32_t(N) : 0u;
+    int shift = 7;
+    while ((1 << shift) < 128 * m)
+        ++shift;
+    s->win_shift = uint32_t(shift);
+    s->win_tiles = uint32_t(((1 << shift) - 1) / kTileConf);
+    s->K_pad = ((s->K + s->U + 2 + 31) / 32) * 32;
+    if (s->K_pad / 32 > uint32_t(kMaxKB)) {
+        *msg = "product depth exceeds the compiled kernels";
+        return HP_EUNSUPPORTED;
+    }
+    s->planes = 0;
+    if (B)
+        while ((1u << s->planes) <= cmax)
+            ++s->planes;
+    s->uw = N > 32 ? 2 : 1;
+    s->MW = s->W + s->planes * s->uw;
+
+    // ---- contact bitmasks and the int8 contact matrix ----------------------
+    s->masks.assign(size_t(n_conf) * s->MW, 0);
+    const uint32_t KB = s->K_pad / 32;
+    const uint32_t n_tiles = (n_conf + kTileConf - 1) / kTileConf;
+    const uint32_t wconf = s->win_tiles * kTileConf;
+    s->gemm_a.assign(size_t(n_tiles) * KB * 1024, 0);
+    auto a_byte = [&](uint32_t c, uint32_t k) -> int8_t & {
+        uint32_t t = c / kTileConf, col = c % kTileConf;
+        uint32_t kb = k / 32, kk = k % 32;
+        uint32_t lane = col + 32 * (kk / 16);
+        return s->gemm_a[((size_t(t) * KB + kb) * 64 + lane) * 16 + kk % 16];
+    };
+    for (uint32_t c = 0; c < n_conf; ++c) {
+        uint32_t *mask = &s->masks[size_t(c) * s->MW];
+        for (uint32_t q = 0; q < s->nbp; ++q) {
+            const int i = s->contacts[(size_t(c) * s->nbp + q) * 2];
+            const int j = s->contacts[(size_t(c) * s->nbp + q) * 2 + 1];
+            const int k = pidx[size_t(i) * N + j];
+            mask[k / 32] |= 1u << (k % 32);
+            a_byte(c, k) = static_cast<int8_t>(-A * m);
+        }
+        for (uint32_t i = 0; i < s->U; ++i) {
+            const uint32_t ci = deg[size_t(c) * N + i];
+            a_byte(c, s->K + i) = static_cast<int8_t>(-B * int64_t(ci) * m);
+            for (uint32_t b = 0; b < s->planes; ++b)
+                if ((ci >> b) & 1u)
+                    mask[s->W + b * s->uw + i / 32] |= 1u << (i % 32);
+        }
         // index rows: key low bits = position of c inside its window, plus 1;
         // padding columns keep all-zero rows, i.e. key 0 = "no conformation"
-        const uint32_t idx1 = c % kWindowConf + 1;
-        a_byte(c, s->K) = static_cast<int8_t>(idx1 & 127);
-        a_byte(c, s->K + 1) = static_cast<int8_t>(-static_cast<int>(idx1 >> 7));
+        const uint32_t idx1 = c % wconf + 1;
+        a_byte(c, s->K + s->U) = static_cast<int8_t>(idx1 & 127);
+        a_byte(c, s->K + s->U + 1) = static_cast<int8_t>(-static_cast<int>(idx1 >> 7));
     }
 
-    // B-operand row table, 4 bytes per row (i, j, c, 0): the kernels form the
-    // byte 0x80 * h_i h_j | c.  Rows beyond the pairs use monomer 63, which is
-    // always P, so only their constant c remains: 0x01 and 0x80 for the two
-    // index rows, 0 for padding.
+    // pair table for the popcount form, 4 bytes per row (i, j, 0, 0)
     s->pair_rows.assign(size_t(s->K_pad) * 4, 0);
     for (uint32_t k = 0; k < s->K_pad; ++k) {
         uint8_t *r = &s->pair_rows[size_t(k) * 4];
-        if (k < s->K) {
-            r[0] = s->pairs[2 * k];
-            r[1] = s->pairs[2 * k + 1];
-        } else {
-            r[0] = r[1] = 63;
-            r[2] = k == s->K ? 0x01 : (k == s->K + 1 ? 0x80 : 0x00);
-        }
+        r[0] = k < s->K ? s->pairs[2 * k] : 63;
+        r[1] = k < s->K ? s->pairs[2 * k + 1] : 63;
     }
 
     // ---- workspace layout ---------------------------------------------------

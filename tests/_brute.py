@@ -83,11 +83,13 @@ def contacts(walk, X, Y):
     return {(i, j) for i in range(N) for j in range(i + 2, N) if adjacent(xyz(walk[i]), xyz(walk[j]))}
 
 
-def energy(s, cts):
-    return -sum(((s >> i) & 1) * ((s >> j) & 1) for i, j in cts)
+def energy(s, cts, table=None):
+    if table is None:
+        return -sum(((s >> i) & 1) * ((s >> j) & 1) for i, j in cts)
+    return sum(table[2 * ((s >> i) & 1) + ((s >> j) & 1)] for i, j in cts)
 
 
-def model(X, Y, Z):
+def model(X, Y, Z, table=None):
     """Conformations, classes and the full phenotype map of a tiny box."""
     walks = directed_walks(X, Y, Z)
     G = isometries(X, Y, Z)
@@ -108,7 +110,7 @@ def model(X, Y, Z):
     phen = []
     emin = []
     for s in range(1 << N):
-        es = {w: energy(s, wct[w]) for w in walks}
+        es = {w: energy(s, wct[w], table) for w in walks}
         m = min(es.values())
         winners = {wkey[w] for w in walks if es[w] == m}
         emin.append(m)

@@ -140,3 +140,29 @@ def test_workspace_layout(lib):
     n_tiles = (s.n_conf + 31) // 32
     assert n >= s.n_conf * 2 + s.n_conf * s.W * 4 + n_tiles * 32 * s.K_pad
     assert n % 256 == 0
+
+
+def test_energy_table_structures(lib):
+    import oracle
+    for dims in [(3, 3, 3), (6, 6, 1), (4, 4, 1)]:
+        st = oracle.structures(*dims)
+        s = hp.Structures(*dims, table=(0, -10, -10, -23))
+        ref = hp.Structures(*dims)
+        assert s.table == (0, -10, -10, -23) and ref.table == (0, 0, 0, -1)
+        assert s.unary_rows == s.N and ref.unary_rows == 0
+        assert s.K_pad == ((s.K + s.N + 2 + 31) // 32) * 32
+        deg = np.zeros((st.n_conf, st.N), int)
+        for c in range(st.n_conf):
+            for i, j in st.pairs[st.ct_off[c]:st.ct_off[c + 1]].tolist():
+                deg[c, i] += 1
+                deg[c, j] += 1
+        assert s.cmax == deg.max()
+        assert np.array_equal(s.export()["contacts"], ref.export()["contacts"])
+    h = ctypes.c_void_p()
+    bad = (ctypes.c_int32 * 4)(0, -10, -11, -23)         # asymmetric
+    assert lib.hp_structures_energy(3, 3, 1, bad, ctypes.byref(h)) == -1
+    rep = (ctypes.c_int32 * 4)(0, 5, 5, -1)              # repulsive H-P contacts
+    assert lib.hp_structures_energy(3, 3, 1, rep, ctypes.byref(h)) == -5
+    big = (ctypes.c_int32 * 4)(0, -100, -100, -300)       # weights beyond int8
+    assert lib.hp_structures_energy(3, 3, 3, big, ctypes.byref(h)) == -5
+    assert lib.hp_structures_energy(3, 3, 1, None, ctypes.byref(h)) == -1

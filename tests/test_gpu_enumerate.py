@@ -172,3 +172,48 @@ def test_full_3x3x3_map_gemm():
     for lo in [int(x) for x in rng.integers(0, (1 << 27) - 64, 6)]:
         gs = oracle.ground_states(st, lo, lo + 64)
         assert np.array_equal(out[lo:lo + 64].cpu().numpy().view(np.uint16), gs.out)
+
+
+HP1996_X10 = (0, -10, -10, -23)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("dims", [(2, 2, 1), (2, 3, 1), (3, 3, 1), (2, 2, 2), (3, 4, 1),
+                                  (4, 4, 1), (2, 3, 3)])
+def test_table_full_small_lattices(dims, form):
+    import torch
+    N = dims[0] * dims[1] * dims[2]
+    s = hp.Structures(*dims, table=HP1996_X10)
+    ws = s.workspace()
+    n = 1 << N
+    o = torch.empty(n, dtype=torch.int16, device="cuda")
+    e = torch.empty(n, dtype=torch.int32, device="cuda")
+    d = torch.zeros(s.n_class, dtype=torch.int64, device="cuda")
+    nd = torch.zeros(1, dtype=torch.int64, device="cuda")
+    hp.hp_enumerate(s, ws, form, 0, n, o, e, d, nd)
+    torch.cuda.synchronize()
+    gs = oracle.ground_states(oracle.structures(*dims), 0, n, table=HP1996_X10)
+    _assert_equal({"out": o.cpu().numpy().view(np.uint16), "emin": e.cpu().numpy(),
+                   "desig": d.cpu().numpy().view(np.uint64), "nondesign": int(nd.item())}, gs)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("dims,size", [((3, 3, 3), 1000), ((6, 6, 1), 900), ((2, 3, 4), 700)])
+def test_table_config_windows(dims, size, form):
+    import torch
+    N = dims[0] * dims[1] * dims[2]
+    s = hp.Structures(*dims, table=HP1996_X10)
+    ws = s.workspace()
+    st = oracle.structures(*dims)
+    for lo, hi in _windows(N, size, 1996 + N)[:4]:
+        n = hi - lo
+        o = torch.empty(n, dtype=torch.int16, device="cuda")
+        e = torch.empty(n, dtype=torch.int32, device="cuda")
+        d = torch.zeros(s.n_class, dtype=torch.int64, device="cuda")
+        nd = torch.zeros(1, dtype=torch.int64, device="cuda")
+        print("table window", dims, form, lo, hi, flush=True)
+        hp.hp_enumerate(s, ws, form, lo, hi, o, e, d, nd)
+        torch.cuda.synchronize()
+        gs = oracle.ground_states(st, lo, hi, table=HP1996_X10)
+        _assert_equal({"out": o.cpu().numpy().view(np.uint16), "emin": e.cpu().numpy(),
+                       "desig": d.cpu().numpy().view(np.uint64), "nondesign": int(nd.item())}, gs)

@@ -1,0 +1,97 @@
+"""The full 3x3x3 map with the paper's HP contact table (Table 1, scaled by
+10) against every number the paper prints for it.
+
+Phenotype denominators are the designable phenotypes (47449) unless the
+printed figure only fits the full fold set; the test prints both when they
+differ.  The oracle is not involved: these are the paper's own values.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2008_05612_amd as hp
+from tests.conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_hp1996_3x3x3.txt")
+HP1996_X10 = (0, -10, -10, -23)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _golden():
+    rows = {}
+    for line in open(GOLD):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, val, prec = line.split()[:3]
+        rows[name] = (float(val), float(prec))
+    return rows
+
+
+@pytest.fixture(scope="module")
+def hp1996_map():
+    import torch
+    s = hp.Structures(3, 3, 3, table=HP1996_X10)
+    ws = s.workspace()
+    total = 1 << 27
+    out = torch.empty(total, dtype=torch.int16, device="cuda")
+    d = torch.zeros(s.n_class, dtype=torch.int64, device="cuda")
+    nd = torch.zeros(1, dtype=torch.int64, device="cuda")
+    print("HP1996 3x3x3 full map", flush=True)
+    hp.hp_enumerate(s, ws, hp.FORM_GEMM_I8, 0, total, out, None, d, nd)
+    torch.cuda.synchronize()
+    desig = d.cpu().numpy().view(np.uint64)
+    top = int(desig.argmax())
+    z = lambda n: torch.zeros(n, dtype=torch.int64, device="cuda")  # noqa: E731
+    neu, dele, oth, row = z(s.n_class), z(s.n_class), z(s.n_class), z(s.n_class + 1)
+    hp.hp_neighbors(s, out, neu, dele, oth, top, row)
+    torch.cuda.synchronize()
+    u = lambda t: t.cpu().numpy().view(np.uint64)  # noqa: E731
+    return s, desig, int(nd.item()), top, u(neu), u(dele), u(oth), u(row)
+
+
+def _near(name, got, gold):
+    val, prec = gold[name]
+    print("%-26s paper %-10g got %.6g" % (name, val, got), flush=True)
+    assert abs(got - val) <= prec + 1e-12, name
+
+
+def test_counts_match_the_paper(hp1996_map):
+    s, desig, nondes, top, *_ = hp1996_map
+    g = _golden()
+    total = 1 << 27
+    assert int(desig.sum()) + nondes == total
+    _near("n_class", s.n_class, g)
+    _near("undesignable_classes", int((desig == 0).sum()), g)
+    _near("designable_classes", int((desig > 0).sum()), g)
+    _near("designing_percent", 100.0 * float(desig.sum()) / total, g)
+    _near("deleterious_percent", 100.0 * nondes / total, g)
+    _near("top_designability", int(desig[top]), g)
+
+
+def test_neighbourhood_statistics_match_the_paper(hp1996_map):
+    s, desig, nondes, top, neu, dele, oth, row = hp1996_map
+    g = _golden()
+    N = 27
+    des = desig > 0
+    nq = desig[des].astype(np.float64)
+    rho = neu[des] / (N * nq)
+    null = nq / float(1 << 27)
+    _near("robust_above_null_percent", 100.0 * float((rho > null).mean()), g)
+    connected = int((row[:s.n_class][des] > 0).sum()) - 1    # other than the top fold itself
+    print("connected to top: %d of %d designable (%.3f%%), of %d folds (%.3f%%)"
+          % (connected, des.sum(), 100.0 * connected / des.sum(), s.n_class,
+             100.0 * connected / s.n_class), flush=True)
+    _near("connected_to_top_percent", 100.0 * connected / float(des.sum()), g)
+    _near("mean_phi_del", float((dele[des] / (N * nq)).mean()), g)
+    iso = int((oth[des] == 0).sum())
+    _near("isolated_phenotypes", iso, g)
+    _near("isolated_percent", 100.0 * iso / float(des.sum()), g)
+    _near("mean_other_percent", 100.0 * float((oth[des] / (N * nq)).mean()), g)
+    _near("connected_percent", 100.0 * (1 - iso / float(des.sum())), g)

@@ -351,3 +351,61 @@ def test_components_match_python(dims):
     # every label is a member of its own component and the smallest one
     assert np.all(lab[des] <= np.arange(1 << st.N)[des])
     assert np.all(gs.out[lab[des]] == gs.out[des])
+
+
+# --------------------------------------------------------------------------
+# Two-letter contact tables (Table 1 of the paper, scaled by 10)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(2, 2, 1), (2, 3, 1), (3, 3, 1), (2, 2, 2)])
+def test_table_ground_states_match_python_brute_force(dims):
+    ref = _brute.model(*dims, table=oracle.HP1996_X10)
+    st = oracle.structures(*dims)
+    gs = oracle.ground_states(st, table=oracle.HP1996_X10)
+    assert gs.out.tolist() == ref["phen"]
+    assert gs.emin.tolist() == ref["emin"]
+
+
+def test_pure_hp_table_is_the_default():
+    st = oracle.structures(4, 4, 1)
+    a = oracle.ground_states(st)
+    b = oracle.ground_states(st, table=oracle.PURE_HP)
+    assert np.array_equal(a.out, b.out) and np.array_equal(a.emin, b.emin)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 1), (2, 2, 3)])
+def test_table_energy_decomposition(dims):
+    # any symmetric two-letter table: E = a n_HH + b sum_i h_i c_i + E_PP NBP
+    # with a = E_HH - 2 E_HP + E_PP, b = E_HP - E_PP, c_i = contacts of i
+    st = oracle.structures(*dims)
+    rng = np.random.default_rng(11)
+    for table in (oracle.HP1996_X10, (3, -5, -5, -17), (-2, 4, 4, -9)):
+        e_pp, e_ph, e_hp, e_hh = table
+        a, b = e_hh - 2 * e_hp + e_pp, e_hp - e_pp
+        for c in range(0, st.n_conf, max(1, st.n_conf // 40)):
+            pc = st.pairs[st.ct_off[c]:st.ct_off[c + 1]]
+            deg = np.zeros(st.N, int)
+            for i, j in pc.tolist():
+                deg[i] += 1
+                deg[j] += 1
+            for s in rng.integers(0, 1 << st.N, 6).tolist():
+                h = [(s >> i) & 1 for i in range(st.N)]
+                n_hh = sum(h[i] * h[j] for i, j in pc.tolist())
+                want = a * n_hh + b * sum(h[i] * deg[i] for i in range(st.N)) + e_pp * len(pc)
+                assert oracle.energy_table(s, pc, table) == want
+
+
+def test_hp1996_map_invariants():
+    st = oracle.structures(3, 4, 1)
+    gs = oracle.ground_states(st, table=oracle.HP1996_X10)
+    _check_map_invariants_table(st, gs, st.N)
+
+
+def _check_map_invariants_table(st, gs, N):
+    assert int(gs.designability.sum()) + gs.nondesign == 1 << N
+    idx = np.arange(1 << N, dtype=np.int64)
+    rev = np.zeros_like(idx)
+    for i in range(N):
+        rev |= ((idx >> i) & 1) << (N - 1 - i)
+    assert np.array_equal(gs.out[rev], gs.out)
+    assert np.all(gs.designability[st.self_rev == 0] % 2 == 0)
