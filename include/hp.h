@@ -148,6 +148,32 @@ hp_status hp_enumerate(const hp_structs *s, const void *d_ws, int form, uint64_t
                        uint64_t *d_designability, uint64_t *d_nondesign, void *stream);
 
 /*
+ * Reversal symmetry (Appendix B: the map is symmetric, so only half of the
+ * sequence-structure relationships need computing).  Reversing the chain
+ * maps the phenotype of s onto that of reverse(s) (bit i <-> bit N-1-i), so
+ * it suffices to score the canonical sequences s <= reverse(s).
+ *   hp_canonical_count   number of canonical sequences (2^(h-1)(2^h+1), times
+ *                        2 for odd N, h = floor(N/2)): about half of 2^N.
+ *   hp_enumerate_symmetric  as hp_enumerate over canonical indices
+ *                        [t_lo, t_hi) (t_hi <= hp_canonical_count): each
+ *                        canonical s fills d_out / d_emin at s AND at
+ *                        reverse(s), so both are full 2^N-entry maps indexed
+ *                        by sequence; designability and the deleterious count
+ *                        add 2 for s != reverse(s) and 1 for palindromes.
+ *                        Over [0, hp_canonical_count) the outputs equal those
+ *                        of hp_enumerate over [0, 2^N).
+ * Canonical index order: with s = (a, m, b) (high h bits, middle bit for odd
+ * N, low h bits) and b' = reverse_h(b), s is canonical iff a <= b'.  Indices
+ * run over m, then over row pairs p < 2^(h-1), each holding row b' = p
+ * (a = 0 .. p) followed by row b' = 2^h - 1 - p (a = 0 .. 2^h - 1 - p), i.e.
+ * 2^h + 1 sequences per pair.
+ */
+uint64_t hp_canonical_count(const hp_structs *s);
+hp_status hp_enumerate_symmetric(const hp_structs *s, const void *d_ws, int form, uint64_t t_lo,
+                                 uint64_t t_hi, uint16_t *d_out, int32_t *d_emin,
+                                 uint64_t *d_designability, uint64_t *d_nondesign, void *stream);
+
+/*
  * Batched launch: several enumeration jobs, possibly of different lattices
  * and uneven sizes, processed by ONE persistent kernel launch that takes
  * fixed-size sequence tiles from a shared work list.  Each job has the

@@ -17,7 +17,9 @@ from ._binding import (  # noqa: F401
     hp_components,
     hp_enumerate,
     hp_autotune,
+    hp_canonical_count,
     hp_enumerate_batch,
+    hp_enumerate_symmetric,
     hp_gemm_select,
     hp_gemm_selected,
     hp_gemm_shapes,

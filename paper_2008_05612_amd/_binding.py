@@ -79,6 +79,8 @@ def library():
         "hp_upload": (st, [vp, vp, sz, vp]),
         "hp_enumerate": (st, [vp, vp, ctypes.c_int, u64, u64, vp, vp, vp, vp, vp]),
         "hp_batch_workspace_bytes": (sz, [ctypes.c_int]),
+        "hp_canonical_count": (u64, [vp]),
+        "hp_enumerate_symmetric": (st, [vp, vp, ctypes.c_int, u64, u64, vp, vp, vp, vp, vp]),
         "hp_enumerate_batch": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp, sz, vp]),
         "hp_graph_capture_batch": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp, sz,
                                         ctypes.POINTER(vp)]),
@@ -231,6 +233,24 @@ def hp_enumerate(s: Structures, ws, form: int, seq_lo: int, seq_hi: int, out=Non
         _ptr(designability, torch.int64, s.n_class, "designability"),
         _ptr(nondesign, torch.int64, 1, "nondesign"),
         _stream_handle(stream)), "hp_enumerate")
+
+
+def hp_canonical_count(s: Structures) -> int:
+    return int(library().hp_canonical_count(s.handle))
+
+
+def hp_enumerate_symmetric(s: Structures, ws, form: int, t_lo: int, t_hi: int, out=None,
+                           emin=None, designability=None, nondesign=None, stream=None):
+    """Canonical sequences with index in [t_lo, t_hi); out / emin are full
+    2^N maps indexed by sequence (written at s and reverse(s))."""
+    import torch
+    n = 1 << s.N
+    _check(library().hp_enumerate_symmetric(
+        s.handle, _ptr(ws, torch.uint8, None, "workspace"), form, t_lo, t_hi,
+        _ptr(out, _U16, n, "out"), _ptr(emin, torch.int32, n, "emin"),
+        _ptr(designability, torch.int64, s.n_class, "designability"),
+        _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)),
+        "hp_enumerate_symmetric")
 
 
 @dataclass

@@ -118,6 +118,8 @@ EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
     j.planes = int32_t(s->planes);
     j.uw = int32_t(s->uw);
     j.MW = int32_t(s->MW);
+    j.sym = 0;
+    j.half_bits = s->N / 2;
     return j;
 }
 
@@ -270,6 +272,43 @@ hp_status hp_enumerate(const hp_structs *s, const void *d_ws, int form, uint64_t
         hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs) : var->launch(j, hs);
         if (e != hipSuccess)
             return device_fail(e, "hp_enumerate launch");
+    }
+    return HP_OK;
+}
+
+uint64_t hp_canonical_count(const hp_structs *s)
+{
+    if (!s)
+        return 0;
+    const uint64_t side = uint64_t(1) << (s->N / 2);
+    return side * (side + 1) / 2 * (s->N % 2 ? 2 : 1);
+}
+
+hp_status hp_enumerate_symmetric(const hp_structs *s, const void *d_ws, int form, uint64_t t_lo,
+                                 uint64_t t_hi, uint16_t *d_out, int32_t *d_emin,
+                                 uint64_t *d_designability, uint64_t *d_nondesign, void *stream)
+{
+    if (!s)
+        return fail(HP_EINVAL, "structures handle is NULL");
+    if (!d_ws)
+        return fail(HP_EINVAL, "workspace pointer is NULL");
+    if (t_lo >= t_hi)
+        return fail(HP_EINVAL, "empty canonical range (t_lo >= t_hi)");
+    if (t_hi > hp_canonical_count(s))
+        return fail(HP_EINVAL, "t_hi exceeds the number of canonical sequences");
+    if (form != HP_FORM_POPCOUNT && form != HP_FORM_GEMM_I8)
+        return fail(HP_EINVAL, "unknown kernel form");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const GemmVariant *var = nullptr;
+    if (form == HP_FORM_GEMM_I8 && !(var = gemm_selected_variant(int(s->K_pad / 32))))
+        return fail(HP_EUNSUPPORTED, "no compiled int8 kernel for this K_pad");
+    for (uint64_t lo = t_lo; lo < t_hi; lo += kBlockSeqs) {
+        const uint64_t hi = std::min(t_hi, lo + kBlockSeqs);
+        EnumJob j = make_enum_job(s, d_ws, lo, hi, d_out, d_emin, d_designability, d_nondesign);
+        j.sym = 1;
+        hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs) : var->launch(j, hs);
+        if (e != hipSuccess)
+            return device_fail(e, "hp_enumerate_symmetric launch");
     }
     return HP_OK;
 }

@@ -64,10 +64,50 @@ __device__ __forceinline__ int window_to_global(int k, int conf_base, int win_sh
     return k == 0 ? 0 : g;
 }
 
+// Bits 0 .. n-1 of x reversed (n <= 32).
+__device__ __forceinline__ uint32_t reverse_bits(uint32_t x, int n)
+{
+    return n ? __builtin_bitreverse32(x) >> (32 - n) : 0u;
+}
+
+// Sequence at index t of the enumeration.  Plain jobs: s = t.  Symmetric jobs
+// enumerate only canonical sequences s <= reverse(s): with h = floor(N/2),
+// s = (a, m, b) = high h bits, middle bit (odd N), low h bits, and
+// reverse(s) = (rev b, m, rev a), so s is canonical iff a <= b' = rev b.  Row
+// b' holds the b' + 1 values a = 0 .. b'; rows p and 2^h - 1 - p together
+// hold 2^h + 1, so the index runs over m, then the row pair p < 2^(h-1), then
+// its 2^h + 1 entries (first row p, then row 2^h - 1 - p).  (For h = 0 there
+// is one row holding a = 0.)  *rs receives reverse(s).
+__device__ __forceinline__ uint64_t sequence_at(const EnumJob &j, uint64_t t, uint64_t *rs)
+{
+    if (!j.sym) {
+        *rs = t;
+        return t;
+    }
+    const int h = j.half_bits;
+    const int mid = j.N & 1;
+    const uint64_t side = uint64_t(1) << h;
+    const uint64_t span = side + 1;                         // entries per row pair
+    const uint64_t per_m = h ? (side >> 1) * span : 1;      // canonical count per middle bit
+    const uint64_t m = t / per_m;
+    const uint64_t r = t - m * per_m;
+    const uint64_t p = h ? r / span : 0;
+    const uint64_t o = r - p * span;
+    const bool first = o <= p;
+    const uint64_t bp = first ? p : side - 1 - p;
+    const uint64_t a = first ? o : o - p - 1;
+    const int hi_shift = h + mid;
+    *rs = (bp << hi_shift) | (m << h) | reverse_bits(uint32_t(a), h);
+    return (a << hi_shift) | (m << h) | reverse_bits(uint32_t(bp), h);
+}
+
 // Final decision for one sequence and the per-sequence outputs.  The keys'
-// high part times fmul is F, and the minimum energy is e0 - F.
-__device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, bool valid, int gb,
-                                                int gs, bool count_lane, int fmul)
+// high part times fmul is F, and the minimum energy is e0 - F.  Plain jobs
+// write at s - lo; symmetric jobs write the full-size maps at s and
+// reverse(s) and count a non-palindromic sequence twice.
+__device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, uint64_t rs,
+                                                bool valid, int gb, int gs, bool count_lane,
+                                                int fmul)
 {
     const int nb = gb >> kKeyConfBits;
     const int ns = gs >> kKeyConfBits;
@@ -75,17 +115,27 @@ __device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, bo
     uint16_t q = HP_NONE;
     if (valid && uniq)   // the clamp keeps the table read in bounds for any key
         q = j.c2q[min(max((gb & int(kMaxConf)) - 1, 0), j.n_conf - 1)];
+    const bool twin = j.sym && rs != s;
     if (valid) {
-        if (j.out)
-            j.out[s - j.lo] = q;
-        if (j.emin)
-            j.emin[s - j.lo] = j.e0 - fmul * nb;
+        const uint64_t at = j.sym ? s : s - j.lo;
+        const int e = j.e0 - fmul * nb;
+        if (j.out) {
+            j.out[at] = q;
+            if (twin)
+                j.out[rs] = q;
+        }
+        if (j.emin) {
+            j.emin[at] = e;
+            if (twin)
+                j.emin[rs] = e;
+        }
         if (uniq && j.desig)
-            atomicAdd(&j.desig[q], 1ull);
+            atomicAdd(&j.desig[q], twin ? 2ull : 1ull);
     }
     const unsigned long long del = __ballot(valid && !uniq);
+    const unsigned long long del2 = __ballot(valid && !uniq && twin);
     if (count_lane && j.nondesign && del)
-        atomicAdd(j.nondesign, (unsigned long long)__popcll(del));
+        atomicAdd(j.nondesign, (unsigned long long)(__popcll(del) + __popcll(del2)));
 }
 
 // B-operand fragments of one lane for T sequences: bytes of product rows
@@ -93,9 +143,10 @@ __device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, bo
 // kbase + q).  Row k < K is the pair (i, i + d) of the k-th odd separation
 // d >= 3 in (d, i) order, and its byte is 0x80 * h_i h_{i+d}; rows K .. K+U-1
 // are the unary rows 0x80 * h_{k-K}; row K+U is the constant 0x01 and row
-// K+U+1 the constant 0x80 (the index rows); rows beyond are 0.  The pair of
-// the first row is found by walking the run lengths N - d; consecutive rows
-// then advance (d, i) incrementally, so no table is read.
+// K+U+1 the constant 0x80 (the index rows); rows beyond are 0.  The row walk
+// needs no table: the pair of the first row is found by skipping whole runs
+// of length N - d, consecutive rows advance (d, i), and after the last run
+// the walk continues with d = 0, where h_i h_{i+d} = h_i is the unary row.
 template <int KB, int T>
 __device__ __forceinline__ void p_fragments(const uint64_t (&s)[T], int half, int N, int K, int U,
                                             v4i (&pf)[T][KB])
@@ -108,6 +159,8 @@ __device__ __forceinline__ void p_fragments(const uint64_t (&s)[T], int half, in
             i -= N - d;
             d += 2;
         }
+        if (d >= N)                     // past the pairs: unary row i = kbase - K
+            d = 0;
         uint32_t w[T][4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -119,21 +172,18 @@ __device__ __forceinline__ void p_fragments(const uint64_t (&s)[T], int half, in
                 const int k = kbase + 4 * q + bb;
                 const int ki = K + U;
                 const uint32_t c = k == ki ? 0x01u : (k == ki + 1 ? 0x80u : 0u);
-                const bool pair = k < K;
-                const bool unary = k >= K && k < ki;
+                const bool real = k < ki;
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
-                    uint32_t bit = 0;
-                    if (pair)
-                        bit = uint32_t((s[t] >> i) & (s[t] >> (i + d)) & 1u);
-                    else if (unary)
-                        bit = uint32_t((s[t] >> (k - K)) & 1u);
+                    const uint32_t bit = real ? uint32_t((s[t] >> i) & (s[t] >> (i + d)) & 1u) : 0u;
                     w[t][q] |= ((bit << 7) | c) << (8 * bb);
                 }
                 ++i;                       // next row: next i, or the next run
-                if (i + d >= N) {
+                if (d > 0 && i + d >= N) {
                     i = 0;
                     d += 2;
+                    if (d >= N)
+                        d = 0;
                 }
             }
         }

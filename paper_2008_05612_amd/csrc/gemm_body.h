@@ -114,10 +114,10 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
 
     v4i pf[T][KB];
     {
-        uint64_t seqs[T];
+        uint64_t seqs[T], revs[T];
 #pragma unroll
         for (int t = 0; t < T; ++t)
-            seqs[t] = seq0 + t * 32 + col;
+            seqs[t] = sequence_at(j, seq0 + t * 32 + col, &revs[t]);
         p_fragments<KB, T>(seqs, half, j.N, j.K, j.U, pf);
     }
 
@@ -257,8 +257,10 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
         const int ob = __shfl_xor(gb[t], 32);
         const int os = __shfl_xor(gs[t], 32);
         top2_merge(gb[t], gs[t], ob, os);
-        const uint64_t s = seq0 + t * 32 + col;
-        finish_sequence(j, s, half == 0 && s < j.hi, gb[t], gs[t], lane == 0, 1);
+        const uint64_t idx = seq0 + t * 32 + col;
+        uint64_t rs;
+        const uint64_t sq = sequence_at(j, idx, &rs);
+        finish_sequence(j, sq, rs, half == 0 && idx < j.hi, gb[t], gs[t], lane == 0, 1);
     }
 }
 

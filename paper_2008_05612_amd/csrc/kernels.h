@@ -25,6 +25,8 @@ struct EnumJob {
     int32_t win_tiles, win_shift;   // int8-form key windows
     int32_t A, B, e0;               // F = A n + B u, E = e0 - F
     int32_t planes, uw, MW;         // popcount form: unary bit planes, words, mask stride
+    int32_t sym;                    // 1: [lo, hi) indexes canonical sequences (s <= rev s)
+    int32_t half_bits;              // floor(N / 2)
 };
 
 // Work list of a batched launch, laid out in the batch workspace.

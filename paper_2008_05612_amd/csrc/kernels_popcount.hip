@@ -41,8 +41,10 @@ __global__ __launch_bounds__(256) void k_popcount(EnumJob j, const uint32_t *__r
                                                   const uint8_t *__restrict__ pairs)
 {
     const uchar4 *rows = reinterpret_cast<const uchar4 *>(pairs);
-    const uint64_t s = j.lo + uint64_t(blockIdx.x) * 256 + threadIdx.x;
-    const bool valid = s < j.hi;
+    const uint64_t idx = j.lo + uint64_t(blockIdx.x) * 256 + threadIdx.x;
+    const bool valid = idx < j.hi;
+    uint64_t rs;
+    const uint64_t s = sequence_at(j, idx, &rs);
     uint32_t P[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(256) void k_popcount(EnumJob j, const uint32_t *__r
             n0 = j.A * n0 + j.B * unary_sum(m + W, j.planes, j.uw, s_lo, s_hi);
         top2_add1(best, second, (n0 << kKeyConfBits) | (c + 1));
     }
-    finish_sequence(j, s, valid, best, second, (threadIdx.x & 63) == 0, UN ? 1 : j.A);
+    finish_sequence(j, s, rs, valid, best, second, (threadIdx.x & 63) == 0, UN ? 1 : j.A);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n)
