@@ -1,16 +1,20 @@
 """Full genotype-phenotype map of one lattice, streamed in sequence blocks.
 
     python -m paper_2008_05612_amd.fullmap --lattice 6x6 [--form gemm|popcount]
-        [--block-bits 30] [--neighbors] [--checkpoint FILE] [--json OUT]
+        [--symmetric] [--block-bits 30] [--neighbors] [--checkpoint FILE] [--json OUT]
 
 Every block of 2^block_bits sequences is one hp_enumerate launch; a progress
-line is printed per block.  The uint16 map stays resident on the device
+line is printed per block.  With --symmetric only the canonical sequences
+s <= reverse(s) are scored (hp_enumerate_symmetric, about half the work),
+each result is written at both s and reverse(s), and the blocks run over
+canonical indices.  The uint16 map stays resident on the device
 (2^36 x 2 B = 137 GB for 6x6) unless --no-map is given.  With --checkpoint,
 the accumulated designability is written after every block and a rerun
 resumes after the last finished block (the map of skipped blocks is then not
 available, so --neighbors is refused on a resumed run).
 
-All device work goes through the C ABI (hp_enumerate, hp_neighbors).
+All device work goes through the C ABI (hp_enumerate, hp_enumerate_symmetric,
+hp_neighbors).
 """
 from __future__ import annotations
 
@@ -31,43 +35,44 @@ def _parse_lattice(text: str):
     return tuple(dims)
 
 
-def _load_checkpoint(path, dims, form, block_bits, n_class):
+def _load_checkpoint(path, dims, form, block_bits, n_class, symmetric):
     if not path or not os.path.exists(path):
         return None
     with open(path) as f:
         ck = json.load(f)
     if (tuple(ck["dims"]) != dims or ck["form"] != form or ck["block_bits"] != block_bits
-            or len(ck["designability"]) != n_class):
+            or len(ck["designability"]) != n_class or ck.get("symmetric", False) != symmetric):
         raise ValueError("checkpoint %s is for another run" % path)
     return ck
 
 
-def _save_checkpoint(path, dims, form, block_bits, next_block, desig, nondesign):
+def _save_checkpoint(path, dims, form, block_bits, symmetric, next_block, desig, nondesign):
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump({"dims": list(dims), "form": form, "block_bits": block_bits,
-                   "next_block": next_block, "designability": [int(x) for x in desig],
-                   "nondesign": int(nondesign)}, f)
+                   "symmetric": symmetric, "next_block": next_block,
+                   "designability": [int(x) for x in desig], "nondesign": int(nondesign)}, f)
     os.replace(tmp, path)
 
 
 def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=False,
-        checkpoint=None, progress=print, device="cuda"):
+        checkpoint=None, progress=print, device="cuda", symmetric=False, table=None):
     """Enumerate all 2^N sequences of the box; returns a summary dict (and the
     device map under key "map" when keep_map)."""
     import numpy as np
     import torch
 
-    s = hp.Structures(*dims)
+    s = hp.Structures(*dims, table=table)
     ws = s.workspace(device)
     N = s.N
     total = 1 << N
+    space = hp.hp_canonical_count(s) if symmetric else total   # indices to process
     block = 1 << min(block_bits, N)
-    n_blocks = total // block
+    n_blocks = (space + block - 1) // block
     desig = torch.zeros(s.n_class, dtype=torch.int64, device=device)
     nond = torch.zeros(1, dtype=torch.int64, device=device)
     start_block = 0
-    ck = _load_checkpoint(checkpoint, dims, form, block_bits, s.n_class)
+    ck = _load_checkpoint(checkpoint, dims, form, block_bits, s.n_class, symmetric)
     if ck:
         start_block = ck["next_block"]
         desig.copy_(torch.tensor(np.array(ck["designability"], dtype=np.uint64).view(np.int64)))
@@ -78,13 +83,16 @@ def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=Fals
     out = torch.empty(total, dtype=torch.int16, device=device) if keep_map else None
     t0 = time.time()
     for b in range(start_block, n_blocks):
-        lo, hi = b * block, (b + 1) * block
+        lo, hi = b * block, min((b + 1) * block, space)
         tb = time.time()
-        hp.hp_enumerate(s, ws, form, lo, hi, out[lo:hi] if out is not None else None, None,
-                        desig, nond)
+        if symmetric:
+            hp.hp_enumerate_symmetric(s, ws, form, lo, hi, out, None, desig, nond)
+        else:
+            hp.hp_enumerate(s, ws, form, lo, hi, out[lo:hi] if out is not None else None, None,
+                            desig, nond)
         torch.cuda.synchronize()
         if checkpoint:
-            _save_checkpoint(checkpoint, dims, form, block_bits, b + 1,
+            _save_checkpoint(checkpoint, dims, form, block_bits, symmetric, b + 1,
                              desig.cpu().numpy().view(np.uint64), int(nond.item()))
         progress("block %d/%d [%d, %d) %.2f s" % (b + 1, n_blocks, lo, hi, time.time() - tb))
     wall = time.time() - t0
@@ -94,8 +102,11 @@ def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=Fals
         "lattice": "x".join(str(x) for x in dims if x > 1) or "1",
         "N": N, "sequences": total, "n_conf": s.n_conf, "n_class": s.n_class,
         "form": "gemm_i8" if form == hp.FORM_GEMM_I8 else "popcount",
+        "symmetric": symmetric, "scored_sequences": space,
         "blocks": n_blocks, "block_sequences": block, "resumed_at_block": start_block,
-        "wall_s": wall, "evals_per_s": (n_blocks - start_block) * block * s.n_conf / wall,
+        "wall_s": wall,
+        "evals_per_s": (space - start_block * block) * s.n_conf / wall,
+        "map_evals_per_s": (space - start_block * block) * s.n_conf / wall * (total / space),
         "designing": int(d.sum()), "nondesign": nd,
         "designable_classes": int((d > 0).sum()),
         "top_class": int(d.argmax()), "top_designability": int(d.max()),
@@ -134,6 +145,7 @@ def main(argv=None):
     ap.add_argument("--lattice", default="6x6")
     ap.add_argument("--form", choices=["gemm", "popcount"], default="gemm")
     ap.add_argument("--block-bits", type=int, default=30)
+    ap.add_argument("--symmetric", action="store_true")
     ap.add_argument("--neighbors", action="store_true")
     ap.add_argument("--no-map", action="store_true")
     ap.add_argument("--checkpoint")
@@ -142,7 +154,7 @@ def main(argv=None):
     form = hp.FORM_GEMM_I8 if a.form == "gemm" else hp.FORM_POPCOUNT
     res = run(_parse_lattice(a.lattice), form, a.block_bits, keep_map=not a.no_map,
               neighbors=a.neighbors, checkpoint=a.checkpoint,
-              progress=lambda m: print(m, flush=True))
+              progress=lambda m: print(m, flush=True), symmetric=a.symmetric)
     pub = {k: v for k, v in res.items() if not k.startswith("_") and k != "map"}
     line = json.dumps(pub)
     print(line, flush=True)

@@ -53,11 +53,33 @@ def test_checkpoint_resume_is_identical(tmp_path):
     assert np.array_equal(ref["_designability"], gs.designability)
 
 
+def test_checkpoint_resume_symmetric(tmp_path):
+    dims = (4, 4, 1)
+    ref = fullmap.run(dims, block_bits=10, keep_map=False, progress=lambda m: None)
+    ck = str(tmp_path / "cks.json")
+    seen = []
+
+    def stop_after_two(msg):
+        seen.append(msg)
+        if len(seen) == 2:
+            raise _Stop()
+
+    with pytest.raises(_Stop):
+        fullmap.run(dims, block_bits=10, keep_map=False, checkpoint=ck, symmetric=True,
+                    progress=stop_after_two)
+    res = fullmap.run(dims, block_bits=10, keep_map=False, checkpoint=ck, symmetric=True,
+                      progress=lambda m: None)
+    assert res["resumed_at_block"] == 2 and res["scored_sequences"] < 1 << 16
+    assert np.array_equal(res["_designability"], ref["_designability"])
+    assert res["nondesign"] == ref["nondesign"]
+
+
 @pytest.mark.skipif(os.environ.get("HP_RUN_FULLMAP") != "1",
-                    reason="full 6x6 map takes ~11 min; set HP_RUN_FULLMAP=1")
+                    reason="full 6x6 map takes ~6 min; set HP_RUN_FULLMAP=1")
 def test_full_6x6_map():
     import torch
-    res = fullmap.run((6, 6, 1), neighbors=True, progress=lambda m: print(m, flush=True))
+    res = fullmap.run((6, 6, 1), neighbors=True, symmetric=True,
+                      progress=lambda m: print(m, flush=True))
     pub = {k: v for k, v in res.items() if not k.startswith("_") and k != "map"}
     print(json.dumps(pub), flush=True)
     out = res["map"]
