@@ -66,6 +66,10 @@ def lib():
                                         u64p, u64p]),
             "or_ground_states_brute": (None, [c_int, c_int, c_int, u8p, c_long, c_u64, c_u64,
                                               u16p, i32p]),
+            "or_ground_states_gap": (None, [c_long, i32p, u8p, i32p, i32p, u64p, c_long, c_int,
+                                            u16p, i32p, u8p, u64p, u64p]),
+            "or_splitmix64": (c_u64, [c_u64, c_u64]),
+            "or_sample_sequences": (None, [c_u64, c_u64, c_u64, c_int, u64p]),
             "or_neighbors": (None, [c_int, u16p, c_long, u64p, u64p, u64p, c_int, u64p]),
             "or_components": (None, [c_int, u16p, u32p]),
             "or_num_threads": (c_int, []),
@@ -242,6 +246,50 @@ def ground_states(st: Structures, lo: int = 0, hi: int | None = None,
                            _p(emin, ctypes.c_int32), _p(desig, ctypes.c_uint64),
                            _p(nond, ctypes.c_uint64))
     return GroundStates(out[:n], emin[:n], desig[:st.n_class], int(nond[0]))
+
+
+@dataclass
+class GapStates:
+    out: np.ndarray             # uint16 phenotype per listed sequence
+    emin: np.ndarray            # int32 lowest energy
+    gap: np.ndarray             # uint8 second-lowest minus lowest energy, saturated at 255
+    designability: np.ndarray   # uint64 per class
+    nondesign: int
+
+
+def ground_states_gap(st: Structures, seqs, threshold: int = 1, table=None) -> GapStates:
+    """Lowest energy, energy gap and thresholded phenotype of each sequence
+    in `seqs` (any order, repeats allowed); `table` as in ground_states."""
+    q = np.ascontiguousarray(np.asarray(seqs, dtype=np.uint64).reshape(-1))
+    n = q.shape[0]
+    out = np.zeros(max(n, 1), dtype=np.uint16)
+    emin = np.zeros(max(n, 1), dtype=np.int32)
+    gap = np.zeros(max(n, 1), dtype=np.uint8)
+    desig = np.zeros(max(st.n_class, 1), dtype=np.uint64)
+    nond = np.zeros(1, dtype=np.uint64)
+    t = np.ascontiguousarray(np.asarray(PURE_HP if table is None else table, dtype=np.int32))
+    if n:
+        lib().or_ground_states_gap(st.n_conf, _p(st.ct_off, ctypes.c_int32),
+                                   _p(st.pairs, ctypes.c_uint8),
+                                   _p(st.conf_to_class, ctypes.c_int32), _p(t, ctypes.c_int32),
+                                   _p(q, ctypes.c_uint64), n, int(threshold),
+                                   _p(out, ctypes.c_uint16), _p(emin, ctypes.c_int32),
+                                   _p(gap, ctypes.c_uint8), _p(desig, ctypes.c_uint64),
+                                   _p(nond, ctypes.c_uint64))
+    return GapStates(out[:n], emin[:n], gap[:n], desig[:st.n_class], int(nond[0]))
+
+
+def splitmix64(seed: int, i: int) -> int:
+    """Draw i (0-based) of the splitmix64 stream seeded with `seed`."""
+    return int(lib().or_splitmix64(seed & (2**64 - 1), i))
+
+
+def sample_sequences(seed: int, lo: int, hi: int, N: int) -> np.ndarray:
+    """Random sequences lo .. hi-1 of the sampling mode (uint64, low N bits)."""
+    out = np.zeros(max(hi - lo, 1), dtype=np.uint64)
+    if hi > lo:
+        lib().or_sample_sequences(seed & (2**64 - 1), lo, hi, N, _p(out, ctypes.c_uint64))
+    return out[:hi - lo]
 
 
 def ground_states_brute(st: Structures, lo: int = 0, hi: int | None = None):

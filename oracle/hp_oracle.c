@@ -18,6 +18,11 @@
  *     minimum energy; otherwise it has the deleterious phenotype (Methods,
  *     end of "HP and MJ lattice models"; the min/second-min test of the GPU
  *     listing in Appendix C).
+ *   - With an energy threshold (Methods, same passage) a sequence folds iff the
+ *     second-lowest conformation energy exceeds the lowest by at least the
+ *     threshold; threshold 1 with integer energies is the uniqueness rule.
+ *     Random sequences for the sampling mode come from a published
+ *     counter-based generator (splitmix64).
  *   - Designability N_q, the neighbourhood counts behind phi_pq, robustness and
  *     phi_del (Eq. 2 and the text around it), and neutral-network components
  *     are plain counts over the 2^N hypercube of sequences.
@@ -502,6 +507,90 @@ void or_ground_states_table(long n_conf, const int32_t *ct_off, const uint8_t *p
     }
     if (!out)
         free(res);
+}
+
+/* Energy gap and threshold (Methods, end of "HP and MJ lattice models": a
+ * threshold sets the smallest energy difference between the lowest and the
+ * second-lowest fold that counts as distinguishable; a sequence whose two
+ * lowest folds lie closer than that does not fold).  For each listed
+ * sequence seqs[t], with E1 <= E2 the two smallest energies over all
+ * conformations (E2 = E1 when the minimum is shared):
+ *   emin[t] = E1;  gap[t] = min(E2 - E1, 255), or 255 with one conformation;
+ *   out[t]  = class of the minimiser if E2 - E1 >= threshold, else 0xFFFF.
+ * threshold = 1 is the plain uniqueness rule.  Energies use the contact
+ * table {E_PP, E_PH, E_HP, E_HH} (or_energy_table).  designability[q] and
+ * *nondesign are incremented (+=).  Any output pointer may be NULL.        */
+void or_ground_states_gap(long n_conf, const int32_t *ct_off, const uint8_t *pairs,
+                          const int32_t *conf_to_class, const int32_t *table,
+                          const uint64_t *seqs, long count, int threshold, uint16_t *out,
+                          int32_t *emin, uint8_t *gap, uint64_t *designability,
+                          uint64_t *nondesign)
+{
+    uint16_t *res = out ? out : (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(count > 0 ? count : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long t = 0; t < count; t++) {
+        uint64_t s = seqs[t];
+        long e1 = 0, e2 = 0;      /* valid once 1 and 2 conformations are seen */
+        long seen = 0;
+        long arg = -1;
+        for (long c = 0; c < n_conf; c++) {
+            long e = or_energy_table(s, ct_off[c + 1] - ct_off[c], pairs + 2 * (size_t)ct_off[c],
+                                     table);
+            if (seen == 0 || e < e1) {
+                e2 = e1;
+                e1 = e;
+                arg = c;
+            } else if (seen == 1 || e < e2) {
+                e2 = e;
+            }
+            seen++;
+        }
+        long g = seen >= 2 ? e2 - e1 : 255;
+        if (g > 255)
+            g = 255;
+        if (emin)
+            emin[t] = (int32_t)e1;
+        if (gap)
+            gap[t] = (uint8_t)g;
+        res[t] = (seen >= 1 && g >= threshold) ? (uint16_t)conf_to_class[arg] : (uint16_t)OR_NONE;
+    }
+    for (long t = 0; t < count; t++) {
+        if (res[t] == OR_NONE) {
+            if (nondesign)
+                (*nondesign)++;
+        } else if (designability) {
+            designability[res[t]]++;
+        }
+    }
+    if (!out)
+        free(res);
+}
+
+/* Random sequences for the sampling mode (Methods: where enumerating every
+ * sequence is out of reach, sequences with independent equiprobable H/P
+ * monomers are drawn instead).  The draws come from splitmix64 (Steele, Lea
+ * and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014),
+ * used as a counter-based generator: draw i of the stream seeded with x is
+ * mix(x + (i + 1) * 0x9E3779B97F4A7C15) with the variant-13 mixing function
+ * z ^= z >> 30; z *= 0xBF58476D1CE4E5B9; z ^= z >> 27;
+ * z *= 0x94D049BB133111EB; z ^= z >> 31.  Sample i is the low N bits of
+ * draw i, i.e. N independent fair coin flips.                              */
+uint64_t or_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * UINT64_C(0x9E3779B97F4A7C15);
+    z ^= z >> 30;
+    z *= UINT64_C(0xBF58476D1CE4E5B9);
+    z ^= z >> 27;
+    z *= UINT64_C(0x94D049BB133111EB);
+    z ^= z >> 31;
+    return z;
+}
+
+void or_sample_sequences(uint64_t seed, uint64_t lo, uint64_t hi, int N, uint64_t *out)
+{
+    uint64_t mask = N >= 64 ? ~UINT64_C(0) : ((UINT64_C(1) << N) - 1);
+    for (uint64_t i = lo; i < hi; i++)
+        out[i - lo] = or_splitmix64(seed, i) & mask;
 }
 
 /* Ground states for every sequence s in [lo, hi):

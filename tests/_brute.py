@@ -126,6 +126,37 @@ def model(X, Y, Z, table=None):
     }
 
 
+def gap_model(X, Y, Z, seqs, threshold=1, table=None):
+    """Energy gap and thresholded phenotype of each listed sequence, scoring
+    every directed walk: conformation energies are grouped by orbit key and
+    sorted; gap = second - first (255 with one conformation, capped at 255)."""
+    walks = directed_walks(X, Y, Z)
+    G = isometries(X, Y, Z)
+
+    def key(w):
+        return min(tuple(g[s] for s in w) for g in G)
+
+    wkey = {w: key(w) for w in walks}
+
+    def class_key(k):
+        return min(k, key(tuple(reversed(k))))
+
+    class_keys = sorted({class_key(k) for k in wkey.values()})
+    cidx = {k: i for i, k in enumerate(class_keys)}
+    wct = {w: contacts(w, X, Y) for w in walks}
+    res = []
+    for s in seqs:
+        conf_e = {}
+        for w in walks:
+            e = energy(s, wct[w], table)
+            assert conf_e.setdefault(wkey[w], e) == e   # isometries keep the contacts
+        ranked = sorted(conf_e.items(), key=lambda kv: kv[1])
+        gap = 255 if len(ranked) < 2 else min(ranked[1][1] - ranked[0][1], 255)
+        phen = cidx[class_key(ranked[0][0])] if gap >= threshold else NONE
+        res.append((phen, ranked[0][1], gap))
+    return res
+
+
 def hamiltonian_path_count(X, Y, Z):
     """Directed Hamiltonian paths by dynamic programming over visited sets
     (an algorithm unrelated to depth-first search)."""

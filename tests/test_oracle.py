@@ -409,3 +409,96 @@ def _check_map_invariants_table(st, gs, N):
         rev |= ((idx >> i) & 1) << (N - 1 - i)
     assert np.array_equal(gs.out[rev], gs.out)
     assert np.all(gs.designability[st.self_rev == 0] % 2 == 0)
+
+
+# --------------------------------------------------------------------------
+# Energy gap, threshold and random sampling
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(2, 2, 1), (2, 3, 1), (3, 3, 1), (2, 2, 2)])
+@pytest.mark.parametrize("table,thresholds", [(None, (1, 2, 3)),
+                                              (oracle.HP1996_X10, (1, 7, 10, 13, 30))])
+def test_gap_matches_python_brute_force(dims, table, thresholds):
+    st = oracle.structures(*dims)
+    seqs = list(range(1 << st.N))
+    for thr in thresholds:
+        ref = _brute.gap_model(*dims, seqs, thr, table)
+        g = oracle.ground_states_gap(st, seqs, thr, table)
+        assert g.out.tolist() == [r[0] for r in ref]
+        assert g.emin.tolist() == [r[1] for r in ref]
+        assert g.gap.tolist() == [r[2] for r in ref]
+
+
+def test_gap_matches_python_brute_force_3x4_sample():
+    st = oracle.structures(3, 4, 1)
+    seqs = np.random.default_rng(5).integers(0, 1 << st.N, 200).tolist()
+    for table, thr in ((None, 2), (oracle.HP1996_X10, 10)):
+        ref = _brute.gap_model(3, 4, 1, seqs, thr, table)
+        g = oracle.ground_states_gap(st, seqs, thr, table)
+        assert [tuple(x) for x in zip(g.out.tolist(), g.emin.tolist(), g.gap.tolist())] == ref
+
+
+def test_gap_hand_derived_3x3():
+    # H at {1,3,8}: energies SI -2, SO -1, SN -1, C1 0, C2 -1 -> gap 1;
+    # H at {0,7}: three-way tie at -1 -> gap 0; 2x2 has one conformation.
+    st = oracle.structures(3, 3, 1)
+    g = oracle.ground_states_gap(st, [266, 129], threshold=1)
+    assert g.gap.tolist() == [1, 0] and g.emin.tolist() == [-2, -1]
+    assert g.out[0] != oracle.NONE and g.out[1] == oracle.NONE
+    g2 = oracle.ground_states_gap(st, [266], threshold=2)
+    assert g2.out[0] == oracle.NONE and g2.nondesign == 1
+    one = oracle.ground_states_gap(oracle.structures(2, 2, 1), range(16), threshold=255)
+    assert np.all(one.gap == 255) and np.all(one.out == 0)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 1), (2, 2, 3)])
+def test_gap_closed_forms_and_threshold_monotone(dims):
+    st = oracle.structures(*dims)
+    N = st.N
+    seqs = np.arange(1 << N, dtype=np.uint64)
+    nbp = st.ct_off[1] - st.ct_off[0]
+    base = oracle.ground_states(st)
+    prev = None
+    for thr in range(1, 6):
+        g = oracle.ground_states_gap(st, seqs, thr)
+        # threshold 1 is the uniqueness rule (the map pinned above)
+        if thr == 1:
+            assert np.array_equal(g.out, base.out) and np.array_equal(g.emin, base.emin)
+        assert np.array_equal(g.out != oracle.NONE, g.gap >= thr)
+        assert np.all(g.gap <= nbp)
+        assert int(g.designability.sum()) + g.nondesign == 1 << N
+        if prev is not None:
+            assert np.all(g.designability <= prev.designability)
+            kept = g.out != oracle.NONE
+            assert np.array_equal(g.out[kept], prev.out[kept])
+        prev = g
+    # all-H and parity-pure sequences tie every conformation: gap 0
+    even = sum(1 << i for i in range(0, N, 2))
+    odd = sum(1 << i for i in range(1, N, 2))
+    g = oracle.ground_states_gap(st, [(1 << N) - 1, even, odd, 0])
+    assert g.gap.tolist() == [0, 0, 0, 0]
+    assert g.emin[0] == -nbp
+
+
+def test_splitmix64_published_values():
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    for i, v in rows:
+        assert oracle.splitmix64(0, int(i)) == int(v, 16)
+
+
+def test_sampled_sequences_are_fair_coin_flips():
+    N = 36
+    seqs = oracle.sample_sequences(0x2008056120, 0, 1 << 16, N)
+    assert seqs.dtype == np.uint64 and np.all(seqs < (1 << N))
+    assert np.array_equal(seqs[100:200], oracle.sample_sequences(0x2008056120, 100, 200, N))
+    n = seqs.shape[0]
+    for i in range(N):
+        ones = int(((seqs >> np.uint64(i)) & np.uint64(1)).sum())
+        assert abs(ones - n / 2) < 5 * np.sqrt(n / 4), i
+    # different seeds give different streams; no repeats among 2^16 36-bit draws is
+    # expected (birthday bound 2^32 / 2^36 = 1/16 chance of one)
+    assert len(np.unique(seqs)) >= n - 2
+    other = oracle.sample_sequences(1, 0, 1 << 10, N)
+    assert not np.array_equal(other, seqs[:1 << 10])
