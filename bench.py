@@ -226,8 +226,9 @@ def recorded_traffic(kname):
 
 
 def extra_measurements(hp, s, ws, dev):
-    """Popcount form on a 2^24 slice of the cube (same GPU), and one 2^28 block
-    of the 6x6 map in both forms, with the full 6x6 time extrapolated."""
+    """Popcount form on a 2^24 slice of the cube (same GPU), the sampling mode
+    on both lattices, and one 2^28 block of the 6x6 map in both forms, with the
+    full 6x6 time extrapolated."""
     import torch
     res = {}
     n = 1 << 24
@@ -246,8 +247,29 @@ def extra_measurements(hp, s, ws, dev):
     # bit counts, 4 for the key and top-2 update)
     res["popcount_valu_frac_3x3x3"] = (res["3x3x3_slice_popcount_evals_per_s"] *
                                        (2 * s.W + 4) / (PEAK_VALU_TOPS * 1e12))
+    # sampling mode (device-side draws): one launch of 2^14 draws -- the
+    # launch size of the paper's sampling runs -- and one of 2^24; the
+    # per-sequence time is the unit of the paper's CPU/GPU comparison table
+    for nd_, name in ((1 << 14, "2^14"), (1 << 24, "2^24")):
+        hp.hp_sample(s, ws, hp.FORM_GEMM_I8, 1, 0, 1 << 14, 1)
+        torch.cuda.synchronize()
+        t.start()
+        hp.hp_sample(s, ws, hp.FORM_GEMM_I8, 0x2008056120, 0, nd_, 1)
+        t.stop()
+        torch.cuda.synchronize()
+        sec = t.ms() * 1e-3
+        res["3x3x3_sample_%s_evals_per_s" % name] = nd_ * s.n_conf / sec
+        res["3x3x3_sample_%s_s_per_sequence" % name] = sec / nd_
     s6 = hp.Structures(6, 6, 1)
     ws6 = s6.workspace()
+    hp.hp_sample(s6, ws6, hp.FORM_GEMM_I8, 1, 0, 1 << 14, 1)
+    torch.cuda.synchronize()
+    t.start()
+    hp.hp_sample(s6, ws6, hp.FORM_GEMM_I8, 0x2008056120, 0, 1 << 22, 1)
+    t.stop()
+    torch.cuda.synchronize()
+    res["6x6_sample_2^22_evals_per_s"] = (1 << 22) * s6.n_conf / (t.ms() * 1e-3)
+    res["6x6_sample_2^22_s_per_sequence"] = t.ms() * 1e-3 / (1 << 22)
     n6 = 1 << 28
     d6 = torch.zeros(s6.n_class, dtype=torch.int64, device=dev)
     for form, name in ((hp.FORM_GEMM_I8, "gemm_i8"), (hp.FORM_POPCOUNT, "popcount")):

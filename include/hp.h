@@ -58,9 +58,18 @@ typedef enum {
 
 #define HP_NONE 0xFFFFu
 
-/* Energy-kernel forms (both give bit-identical results). */
+/* Energy-kernel forms (all give bit-identical results). */
 #define HP_FORM_POPCOUNT 0  /* contact bitmasks, AND + popcount per pair        */
 #define HP_FORM_GEMM_I8 1   /* E = -P.C as an int8 matrix product on MFMA cores */
+/* Block-factorised int8 form: each block of 256 consecutive sequences shares
+ * every monomer above the low 8, so per conformation the energy is a block
+ * term plus weights of the 8 low monomers and their mutual contacts; one
+ * int8 product per 256 sequences forms those (as bytes), a second product of
+ * depth 32 applies them to the sequences.  Needs pure pair energies (a
+ * table with E_HP == E_PP, e.g. pure HP), N >= 8 and A * nbp <= 128 (see
+ * hp_structs_info: unary_rows == 0); only plain ranges (hp_enumerate,
+ * hp_enumerate_gap).  Otherwise HP_EUNSUPPORTED.                          */
+#define HP_FORM_BLOCKED_I8 2
 
 typedef struct hp_structs hp_structs;
 
@@ -119,9 +128,10 @@ hp_status hp_structs_export(const hp_structs *s, uint8_t *walks, uint16_t *conf_
                             uint8_t *contacts);
 
 /*
- * Device workspace holding the packed structure tables both kernel forms
- * read (contact bitmasks, the int8 contact matrix in MFMA operand order,
- * the pair table and conformation-to-class map).  hp_workspace_bytes gives
+ * Device workspace holding the packed structure tables the kernel forms
+ * read (contact bitmasks, the int8 contact matrix in MFMA operand order, the
+ * blocked form's 0/1 contact matrix where it applies, the pair table and the
+ * conformation-to-class map).  hp_workspace_bytes gives
  * its size; hp_upload fills caller memory d_ws (>= that many bytes, 256-byte
  * aligned) asynchronously on `stream`.  The host source stays owned by the
  * handle, so the handle must outlive the copy (synchronise before freeing).
@@ -138,10 +148,11 @@ hp_status hp_upload(const hp_structs *s, void *d_ws, size_t ws_bytes, void *stre
  *   d_designability[q] += number of sequences in range with phenotype q
  *                         (n_class uint64 counters; may be NULL).
  *   d_nondesign[0]     += number of deleterious sequences (may be NULL).
- * `form` selects HP_FORM_POPCOUNT or HP_FORM_GEMM_I8.  d_ws must hold the
- * uploaded workspace of the same handle.
+ * `form` selects HP_FORM_POPCOUNT, HP_FORM_GEMM_I8 or HP_FORM_BLOCKED_I8.
+ * d_ws must hold the uploaded workspace of the same handle.
  * Errors: HP_EINVAL (NULL handle/workspace, empty or out-of-range seq range,
- * unknown form), HP_EDEVICE (launch failure).
+ * unknown form), HP_EUNSUPPORTED (HP_FORM_BLOCKED_I8 for a handle it does not
+ * cover), HP_EDEVICE (launch failure).
  */
 hp_status hp_enumerate(const hp_structs *s, const void *d_ws, int form, uint64_t seq_lo,
                        uint64_t seq_hi, uint16_t *d_out, int32_t *d_emin,
@@ -172,6 +183,46 @@ uint64_t hp_canonical_count(const hp_structs *s);
 hp_status hp_enumerate_symmetric(const hp_structs *s, const void *d_ws, int form, uint64_t t_lo,
                                  uint64_t t_hi, uint16_t *d_out, int32_t *d_emin,
                                  uint64_t *d_designability, uint64_t *d_nondesign, void *stream);
+
+/*
+ * Energy gap and threshold (Methods, end of "HP and MJ lattice models": the
+ * threshold is the smallest difference between the lowest and second-lowest
+ * fold energies that counts as distinguishable; closer than that, the
+ * sequence does not fold).  With E1 <= E2 the two lowest conformation
+ * energies of a sequence (E2 = E1 when the minimum is shared), in the units
+ * of the handle's energy table:
+ *   gap     = E2 - E1, saturated at 255; 255 when the box has one
+ *             conformation;
+ *   folds   iff gap >= threshold (threshold 1 .. 255; 1 is the uniqueness
+ *             rule of hp_enumerate, and integer energies make the two equal).
+ * hp_enumerate_gap  as hp_enumerate, plus the threshold and an optional
+ *                   uint8 d_gap[seq_hi - seq_lo] (device, caller-owned).
+ *                   Designability counts folding sequences only; every other
+ *                   sequence is deleterious (out = HP_NONE).
+ * hp_sample         the random-sampling mode (Methods: sequences are sampled
+ *                   where enumerating all is out of reach), with the sequence
+ *                   draws made on the device.  Draw i (idx_lo <= i < idx_hi
+ *                   <= 2^48) is the low N bits of output i of the splitmix64
+ *                   generator (Steele, Lea and Flood, OOPSLA 2014) seeded
+ *                   with `seed`: z = seed + (i + 1) * 0x9E3779B97F4A7C15,
+ *                   then the variant-13 finaliser (xor-shift 30, multiply
+ *                   0xBF58476D1CE4E5B9, xor-shift 27, multiply
+ *                   0x94D049BB133111EB, xor-shift 31).  Every monomer is H
+ *                   with probability 1/2, independently.  Per-draw outputs are
+ *                   indexed by i - idx_lo: d_seqs (uint64, the drawn
+ *                   sequence), d_out, d_emin, d_gap, each optional.  Draws are
+ *                   with replacement; designability counts draws.
+ * Errors: as hp_enumerate; HP_EINVAL also for a threshold outside 1 .. 255,
+ * an empty draw range or idx_hi > 2^48.
+ */
+hp_status hp_enumerate_gap(const hp_structs *s, const void *d_ws, int form, uint64_t seq_lo,
+                           uint64_t seq_hi, int32_t threshold, uint16_t *d_out, int32_t *d_emin,
+                           uint8_t *d_gap, uint64_t *d_designability, uint64_t *d_nondesign,
+                           void *stream);
+hp_status hp_sample(const hp_structs *s, const void *d_ws, int form, uint64_t seed,
+                    uint64_t idx_lo, uint64_t idx_hi, int32_t threshold, uint64_t *d_seqs,
+                    uint16_t *d_out, int32_t *d_emin, uint8_t *d_gap, uint64_t *d_designability,
+                    uint64_t *d_nondesign, void *stream);
 
 /*
  * Batched launch: several enumeration jobs, possibly of different lattices

@@ -7,6 +7,7 @@ and streams.  If the library is not built, importing works but every call
 raises ``LibraryMissing`` -- there is no fallback path.
 """
 from ._binding import (  # noqa: F401
+    FORM_BLOCKED_I8,
     FORM_GEMM_I8,
     FORM_POPCOUNT,
     NONE,
@@ -19,12 +20,14 @@ from ._binding import (  # noqa: F401
     hp_autotune,
     hp_canonical_count,
     hp_enumerate_batch,
+    hp_enumerate_gap,
     hp_enumerate_symmetric,
     hp_gemm_select,
     hp_gemm_selected,
     hp_gemm_shapes,
     hp_graph_capture_batch,
     hp_neighbors,
+    hp_sample,
     hp_structures,
     hp_upload,
     hp_workspace_bytes,

@@ -18,6 +18,7 @@ _LIB_PATH = os.path.join(_HERE, "libhpmap.so")
 
 FORM_POPCOUNT = 0
 FORM_GEMM_I8 = 1
+FORM_BLOCKED_I8 = 2
 NONE = 0xFFFF
 
 _STATUS = {0: "HP_OK", -1: "HP_EINVAL", -2: "HP_ENOMEM", -3: "HP_EDEVICE", -4: "HP_ERANGE",
@@ -81,6 +82,8 @@ def library():
         "hp_batch_workspace_bytes": (sz, [ctypes.c_int]),
         "hp_canonical_count": (u64, [vp]),
         "hp_enumerate_symmetric": (st, [vp, vp, ctypes.c_int, u64, u64, vp, vp, vp, vp, vp]),
+        "hp_enumerate_gap": (st, [vp, vp, ctypes.c_int, u64, u64, i32, vp, vp, vp, vp, vp, vp]),
+        "hp_sample": (st, [vp, vp, ctypes.c_int, u64, u64, u64, i32, vp, vp, vp, vp, vp, vp, vp]),
         "hp_enumerate_batch": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp, sz, vp]),
         "hp_graph_capture_batch": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp, sz,
                                         ctypes.POINTER(vp)]),
@@ -233,6 +236,35 @@ def hp_enumerate(s: Structures, ws, form: int, seq_lo: int, seq_hi: int, out=Non
         _ptr(designability, torch.int64, s.n_class, "designability"),
         _ptr(nondesign, torch.int64, 1, "nondesign"),
         _stream_handle(stream)), "hp_enumerate")
+
+
+def hp_enumerate_gap(s: Structures, ws, form: int, seq_lo: int, seq_hi: int, threshold: int = 1,
+                     out=None, emin=None, gap=None, designability=None, nondesign=None,
+                     stream=None):
+    """hp_enumerate with an energy-gap threshold and an optional uint8 gap map."""
+    import torch
+    n = seq_hi - seq_lo
+    _check(library().hp_enumerate_gap(
+        s.handle, _ptr(ws, torch.uint8, None, "workspace"), form, seq_lo, seq_hi, threshold,
+        _ptr(out, _U16, n, "out"), _ptr(emin, torch.int32, n, "emin"),
+        _ptr(gap, torch.uint8, n, "gap"),
+        _ptr(designability, torch.int64, s.n_class, "designability"),
+        _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)), "hp_enumerate_gap")
+
+
+def hp_sample(s: Structures, ws, form: int, seed: int, idx_lo: int, idx_hi: int,
+              threshold: int = 1, seqs=None, out=None, emin=None, gap=None, designability=None,
+              nondesign=None, stream=None):
+    """Random-sampling mode: draws idx_lo .. idx_hi-1 of the device generator
+    seeded with `seed`; per-draw outputs are indexed by draw - idx_lo."""
+    import torch
+    n = idx_hi - idx_lo
+    _check(library().hp_sample(
+        s.handle, _ptr(ws, torch.uint8, None, "workspace"), form, seed & (2**64 - 1), idx_lo,
+        idx_hi, threshold, _ptr(seqs, torch.int64, n, "seqs"), _ptr(out, _U16, n, "out"),
+        _ptr(emin, torch.int32, n, "emin"), _ptr(gap, torch.uint8, n, "gap"),
+        _ptr(designability, torch.int64, s.n_class, "designability"),
+        _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)), "hp_sample")
 
 
 def hp_canonical_count(s: Structures) -> int:

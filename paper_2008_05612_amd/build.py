@@ -17,7 +17,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhpmap.so")
 SOURCES = ["structures.cpp", "capi.cpp", "runtime.cpp", "kernels_popcount.hip",
            "gemm_kb1_4.hip", "gemm_kb5.hip", "gemm_kb6_10.hip", "gemm_kb11_12.hip",
-           "gemm_batch.hip",
+           "gemm_batch.hip", "gemm_blk.hip",
            "kernels_net.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -20,6 +20,7 @@ thread_local std::string g_last_error;
 // Sequences per kernel launch of hp_enumerate; longer ranges are streamed as
 // a loop of such blocks (the full 6x6 map is 64 blocks).
 constexpr uint64_t kBlockSeqs = uint64_t(1) << 30;
+constexpr uint64_t kMaxDraws = uint64_t(1) << 48;   // sampled-mode indices per seed
 
 hp_status device_fail(hipError_t e, const char *what)
 {
@@ -97,6 +98,10 @@ EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
     j.pairs = reinterpret_cast<const uint8_t *>(base + s->ws.pairs);
     j.masks = reinterpret_cast<const uint32_t *>(base + s->ws.masks);
     j.gemm_a = reinterpret_cast<const int8_t *>(base + s->ws.gemm_a);
+    j.gemm_b = reinterpret_cast<const int8_t *>(base + s->ws.gemm_b);
+    j.blk_shift = int32_t(s->blk_shift);
+    j.blk_win_tiles = int32_t(s->blk_win_tiles);
+    j.blk_coef = s->blk_coef;
     j.out = out;
     j.emin = emin;
     j.desig = reinterpret_cast<unsigned long long *>(desig);
@@ -118,8 +123,9 @@ EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
     j.planes = int32_t(s->planes);
     j.uw = int32_t(s->uw);
     j.MW = int32_t(s->MW);
-    j.sym = 0;
+    j.mode = kSeqPlain;
     j.half_bits = s->N / 2;
+    j.threshold = 1;
     return j;
 }
 
@@ -240,6 +246,7 @@ hp_status hp_upload(const hp_structs *s, void *d_ws, size_t ws_bytes, void *stre
         {s->ws.pairs, s->pair_rows.data(), s->pair_rows.size()},
         {s->ws.masks, s->masks.data(), s->masks.size() * 4},
         {s->ws.gemm_a, s->gemm_a.data(), s->gemm_a.size()},
+        {s->ws.gemm_b, s->gemm_b.data(), s->gemm_b.size()},
     };
     for (const Part &p : parts) {
         if (!p.bytes)
@@ -251,6 +258,61 @@ hp_status hp_upload(const hp_structs *s, void *d_ws, size_t ws_bytes, void *stre
     return HP_OK;
 }
 
+namespace {
+
+// Options of one enumeration call beyond the plain map.
+struct RunOpts {
+    int mode = kSeqPlain;
+    int threshold = 1;
+    uint64_t seed = 0;
+    uint8_t *gap = nullptr;
+    uint64_t *seqs = nullptr;
+};
+
+// Launches [lo, hi) in blocks of kBlockSeqs indices.  Per-index outputs are
+// offset by the block's position (plain and sampled modes); the designability
+// counters accumulate.
+hp_status run_blocks(const hp_structs *s, const void *d_ws, int form, uint64_t lo_all,
+                     uint64_t hi_all, uint16_t *d_out, int32_t *d_emin, uint64_t *d_designability,
+                     uint64_t *d_nondesign, const RunOpts &o, void *stream, const char *what)
+{
+    if (form != HP_FORM_POPCOUNT && form != HP_FORM_GEMM_I8 && form != HP_FORM_BLOCKED_I8)
+        return fail(HP_EINVAL, "unknown kernel form");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const GemmVariant *var = nullptr;
+    if (form == HP_FORM_GEMM_I8 && !(var = gemm_selected_variant(int(s->K_pad / 32))))
+        return fail(HP_EUNSUPPORTED, "no compiled int8 kernel for this K_pad");
+    if (form == HP_FORM_BLOCKED_I8) {
+        if (o.mode != kSeqPlain)
+            return fail(HP_EUNSUPPORTED, "the blocked form scores plain sequence ranges only");
+        if (!s->blk_ok)
+            return fail(HP_EUNSUPPORTED, "the blocked form needs pure pair energies, N >= 8 "
+                                         "and A * nbp <= 128");
+    }
+    for (uint64_t lo = lo_all; lo < hi_all;) {
+        const uint64_t hi = hi_all - lo > kBlockSeqs ? lo + kBlockSeqs : hi_all;
+        const uint64_t off = lo - lo_all;
+        const bool local = o.mode != kSeqCanonical;   // canonical mode writes full-size maps
+        EnumJob j = make_enum_job(s, d_ws, lo, hi, d_out && local ? d_out + off : d_out,
+                                  d_emin && local ? d_emin + off : d_emin, d_designability,
+                                  d_nondesign);
+        j.mode = o.mode;
+        j.threshold = o.threshold;
+        j.seed = o.seed;
+        j.gap = o.gap && local ? o.gap + off : o.gap;
+        j.seqs = o.seqs ? o.seqs + off : nullptr;
+        hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs)
+                       : form == HP_FORM_BLOCKED_I8 ? launch_gemm_blocked(j, hs)
+                                                    : var->launch(j, hs);
+        if (e != hipSuccess)
+            return device_fail(e, what);
+        lo = hi;
+    }
+    return HP_OK;
+}
+
+}  // namespace
+
 hp_status hp_enumerate(const hp_structs *s, const void *d_ws, int form, uint64_t seq_lo,
                        uint64_t seq_hi, uint16_t *d_out, int32_t *d_emin,
                        uint64_t *d_designability, uint64_t *d_nondesign, void *stream)
@@ -258,22 +320,50 @@ hp_status hp_enumerate(const hp_structs *s, const void *d_ws, int form, uint64_t
     hp_status st = check_range(s, d_ws, seq_lo, seq_hi);
     if (st != HP_OK)
         return st;
-    if (form != HP_FORM_POPCOUNT && form != HP_FORM_GEMM_I8)
-        return fail(HP_EINVAL, "unknown kernel form");
-    hipStream_t hs = static_cast<hipStream_t>(stream);
-    const GemmVariant *var = nullptr;
-    if (form == HP_FORM_GEMM_I8 && !(var = gemm_selected_variant(int(s->K_pad / 32))))
-        return fail(HP_EUNSUPPORTED, "no compiled int8 kernel for this K_pad");
-    for (uint64_t lo = seq_lo; lo < seq_hi; lo += kBlockSeqs) {
-        const uint64_t hi = std::min(seq_hi, lo + kBlockSeqs);
-        EnumJob j = make_enum_job(s, d_ws, lo, hi, d_out ? d_out + (lo - seq_lo) : nullptr,
-                             d_emin ? d_emin + (lo - seq_lo) : nullptr, d_designability,
-                             d_nondesign);
-        hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs) : var->launch(j, hs);
-        if (e != hipSuccess)
-            return device_fail(e, "hp_enumerate launch");
-    }
-    return HP_OK;
+    return run_blocks(s, d_ws, form, seq_lo, seq_hi, d_out, d_emin, d_designability, d_nondesign,
+                      RunOpts{}, stream, "hp_enumerate launch");
+}
+
+hp_status hp_enumerate_gap(const hp_structs *s, const void *d_ws, int form, uint64_t seq_lo,
+                           uint64_t seq_hi, int32_t threshold, uint16_t *d_out, int32_t *d_emin,
+                           uint8_t *d_gap, uint64_t *d_designability, uint64_t *d_nondesign,
+                           void *stream)
+{
+    hp_status st = check_range(s, d_ws, seq_lo, seq_hi);
+    if (st != HP_OK)
+        return st;
+    if (threshold < 1 || threshold > 255)
+        return fail(HP_EINVAL, "threshold must be in 1 .. 255");
+    RunOpts o;
+    o.threshold = threshold;
+    o.gap = d_gap;
+    return run_blocks(s, d_ws, form, seq_lo, seq_hi, d_out, d_emin, d_designability, d_nondesign,
+                      o, stream, "hp_enumerate_gap launch");
+}
+
+hp_status hp_sample(const hp_structs *s, const void *d_ws, int form, uint64_t seed,
+                    uint64_t idx_lo, uint64_t idx_hi, int32_t threshold, uint64_t *d_seqs,
+                    uint16_t *d_out, int32_t *d_emin, uint8_t *d_gap, uint64_t *d_designability,
+                    uint64_t *d_nondesign, void *stream)
+{
+    if (!s)
+        return fail(HP_EINVAL, "structures handle is NULL");
+    if (!d_ws)
+        return fail(HP_EINVAL, "workspace pointer is NULL");
+    if (idx_lo >= idx_hi)
+        return fail(HP_EINVAL, "empty draw range (idx_lo >= idx_hi)");
+    if (idx_hi > kMaxDraws)
+        return fail(HP_EINVAL, "idx_hi exceeds 2^48 draws per seed");
+    if (threshold < 1 || threshold > 255)
+        return fail(HP_EINVAL, "threshold must be in 1 .. 255");
+    RunOpts o;
+    o.mode = kSeqSampled;
+    o.threshold = threshold;
+    o.seed = seed;
+    o.gap = d_gap;
+    o.seqs = d_seqs;
+    return run_blocks(s, d_ws, form, idx_lo, idx_hi, d_out, d_emin, d_designability, d_nondesign,
+                      o, stream, "hp_sample launch");
 }
 
 uint64_t hp_canonical_count(const hp_structs *s)
@@ -296,21 +386,10 @@ hp_status hp_enumerate_symmetric(const hp_structs *s, const void *d_ws, int form
         return fail(HP_EINVAL, "empty canonical range (t_lo >= t_hi)");
     if (t_hi > hp_canonical_count(s))
         return fail(HP_EINVAL, "t_hi exceeds the number of canonical sequences");
-    if (form != HP_FORM_POPCOUNT && form != HP_FORM_GEMM_I8)
-        return fail(HP_EINVAL, "unknown kernel form");
-    hipStream_t hs = static_cast<hipStream_t>(stream);
-    const GemmVariant *var = nullptr;
-    if (form == HP_FORM_GEMM_I8 && !(var = gemm_selected_variant(int(s->K_pad / 32))))
-        return fail(HP_EUNSUPPORTED, "no compiled int8 kernel for this K_pad");
-    for (uint64_t lo = t_lo; lo < t_hi; lo += kBlockSeqs) {
-        const uint64_t hi = std::min(t_hi, lo + kBlockSeqs);
-        EnumJob j = make_enum_job(s, d_ws, lo, hi, d_out, d_emin, d_designability, d_nondesign);
-        j.sym = 1;
-        hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs) : var->launch(j, hs);
-        if (e != hipSuccess)
-            return device_fail(e, "hp_enumerate_symmetric launch");
-    }
-    return HP_OK;
+    RunOpts o;
+    o.mode = kSeqCanonical;
+    return run_blocks(s, d_ws, form, t_lo, t_hi, d_out, d_emin, d_designability, d_nondesign, o,
+                      stream, "hp_enumerate_symmetric launch");
 }
 
 size_t hp_batch_workspace_bytes(int njobs)
@@ -376,7 +455,7 @@ hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *
         return device_fail(e, "capture stream");
     hp_graph *g = new (std::nothrow) hp_graph();
     if (!g) {
-        hipStreamDestroy(cap);
+        (void)hipStreamDestroy(cap);   // cleanup on the error path; its status adds nothing
         return fail(HP_ENOMEM, "out of host memory");
     }
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
@@ -388,7 +467,7 @@ hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *
     }
     if (e == hipSuccess)
         e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-    hipStreamDestroy(cap);
+    (void)hipStreamDestroy(cap);   // the capture's own status decides the result
     if (e != hipSuccess) {
         hp_graph_free(g);
         return device_fail(e, "graph capture");
@@ -410,9 +489,9 @@ void hp_graph_free(hp_graph *g)
     if (!g)
         return;
     if (g->exec)
-        hipGraphExecDestroy(g->exec);
+        (void)hipGraphExecDestroy(g->exec);   // release has no caller to report to
     if (g->graph)
-        hipGraphDestroy(g->graph);
+        (void)hipGraphDestroy(g->graph);
     delete g;
 }
 

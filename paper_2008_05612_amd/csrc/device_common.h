@@ -70,7 +70,20 @@ __device__ __forceinline__ uint32_t reverse_bits(uint32_t x, int n)
     return n ? __builtin_bitreverse32(x) >> (32 - n) : 0u;
 }
 
-// Sequence at index t of the enumeration.  Plain jobs: s = t.  Symmetric jobs
+// Draw t of the splitmix64 stream seeded with `seed` (Steele, Lea and Flood,
+// OOPSLA 2014), evaluated directly from the counter: the generator's state
+// after t + 1 steps is seed + (t + 1) * golden-ratio increment, followed by
+// the variant-13 64-bit finaliser.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t t)
+{
+    uint64_t z = seed + (t + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Sequence at index t of the enumeration.  Plain jobs: s = t.  Sampled jobs:
+// the low N bits of draw t (N independent fair H/P choices).  Symmetric jobs
 // enumerate only canonical sequences s <= reverse(s): with h = floor(N/2),
 // s = (a, m, b) = high h bits, middle bit (odd N), low h bits, and
 // reverse(s) = (rev b, m, rev a), so s is canonical iff a <= b' = rev b.  Row
@@ -80,9 +93,14 @@ __device__ __forceinline__ uint32_t reverse_bits(uint32_t x, int n)
 // is one row holding a = 0.)  *rs receives reverse(s).
 __device__ __forceinline__ uint64_t sequence_at(const EnumJob &j, uint64_t t, uint64_t *rs)
 {
-    if (!j.sym) {
+    if (j.mode == kSeqPlain) {
         *rs = t;
         return t;
+    }
+    if (j.mode == kSeqSampled) {
+        const uint64_t s = splitmix64_at(j.seed, t) & ((uint64_t(1) << j.N) - 1);
+        *rs = s;
+        return s;
     }
     const int h = j.half_bits;
     const int mid = j.N & 1;
@@ -101,23 +119,27 @@ __device__ __forceinline__ uint64_t sequence_at(const EnumJob &j, uint64_t t, ui
     return (a << hi_shift) | (m << h) | reverse_bits(uint32_t(bp), h);
 }
 
-// Final decision for one sequence and the per-sequence outputs.  The keys'
-// high part times fmul is F, and the minimum energy is e0 - F.  Plain jobs
-// write at s - lo; symmetric jobs write the full-size maps at s and
-// reverse(s) and count a non-palindromic sequence twice.
-__device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, uint64_t rs,
-                                                bool valid, int gb, int gs, bool count_lane,
-                                                int fmul)
+// Final decision for sequence s at index t and the per-sequence outputs.
+// The keys' high part times fmul is F, the minimum energy is e0 - F, and the
+// energy gap to the best other conformation is fmul times the difference of
+// the two keys' high parts (0 when the minimum is shared).  The sequence
+// folds iff that gap reaches the threshold, or it has no other conformation.
+// Plain and sampled jobs write at t - lo; symmetric jobs write the full-size
+// maps at s and reverse(s) and count a non-palindromic sequence twice.
+__device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t t, uint64_t s,
+                                                uint64_t rs, bool valid, int gb, int gs,
+                                                bool count_lane, int fmul)
 {
     const int nb = gb >> kKeyConfBits;
     const int ns = gs >> kKeyConfBits;
-    const bool uniq = gs == 0 || nb != ns;   // no second conformation, or a lower one
+    const int diff = fmul * (nb - ns);
+    const bool uniq = gs == 0 || diff >= j.threshold;   // no second conformation, or far enough
     uint16_t q = HP_NONE;
     if (valid && uniq)   // the clamp keeps the table read in bounds for any key
         q = j.c2q[min(max((gb & int(kMaxConf)) - 1, 0), j.n_conf - 1)];
-    const bool twin = j.sym && rs != s;
+    const bool twin = j.mode == kSeqCanonical && rs != s;
     if (valid) {
-        const uint64_t at = j.sym ? s : s - j.lo;
+        const uint64_t at = j.mode == kSeqCanonical ? s : t - j.lo;
         const int e = j.e0 - fmul * nb;
         if (j.out) {
             j.out[at] = q;
@@ -129,6 +151,14 @@ __device__ __forceinline__ void finish_sequence(const EnumJob &j, uint64_t s, ui
             if (twin)
                 j.emin[rs] = e;
         }
+        if (j.gap) {
+            const uint8_t g = uint8_t(gs == 0 ? 255 : min(diff, 255));
+            j.gap[at] = g;
+            if (twin)
+                j.gap[rs] = g;
+        }
+        if (j.seqs)
+            j.seqs[at] = s;
         if (uniq && j.desig)
             atomicAdd(&j.desig[q], twin ? 2ull : 1ull);
     }

@@ -181,6 +181,9 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
                 a[kb] = lds[kb * 64 + lane];
             mma_tile<KB, T>(a, pf, acc0);
         }
+        // Every wave has read tile 0 before any wave overwrites buffer 0
+        // with tile 2 in the first half-step.
+        __syncthreads();
         for (int tile = 0; tile < n_tiles; tile += 2) {
             const bool has1 = tile + 1 < n_tiles;
             const bool has2 = tile + 2 < n_tiles;
@@ -260,7 +263,7 @@ __device__ __forceinline__ void gemm_body(const EnumJob &j, uint64_t seq0_wg, v4
         const uint64_t idx = seq0 + t * 32 + col;
         uint64_t rs;
         const uint64_t sq = sequence_at(j, idx, &rs);
-        finish_sequence(j, sq, rs, half == 0 && idx < j.hi, gb[t], gs[t], lane == 0, 1);
+        finish_sequence(j, idx, sq, rs, half == 0 && idx < j.hi, gb[t], gs[t], lane == 0, 1);
     }
 }
 

@@ -22,6 +22,9 @@ constexpr int kTileConf = 32;        // conformations per MFMA tile (rows of A)
 constexpr int kKeyConfBits = 17;
 constexpr uint32_t kMaxConf = (1u << kKeyConfBits) - 1;
 constexpr int kMaxKB = 12;              // product depth K_pad <= 384
+// Block-factorised int8 form: blocks of 2^kBlkBits consecutive sequences
+// share every monomer above the low kBlkBits.
+constexpr int kBlkBits = 8;
 
 // Byte offsets of the packed tables inside the device workspace.
 struct WsLayout {
@@ -29,6 +32,7 @@ struct WsLayout {
     size_t pairs = 0;    // uint8_t[K_pad][4] row table (i, j, constant, 0)
     size_t masks = 0;    // uint32_t[n_conf][MW]: W pair words, then unary bit planes
     size_t gemm_a = 0;   // int8_t[n_tiles][K_pad/32][64 lanes][16]
+    size_t gemm_b = 0;   // blocked form: int8_t[n_tiles][K_pad/32][64 lanes][16], or none
     size_t total = 0;
 };
 
@@ -47,6 +51,11 @@ struct hp_structs {
     uint32_t planes = 0, uw = 0;      // bit planes of c_i and 32-bit words per plane
     uint32_t MW = 0;                  // mask words per conformation: W + planes * uw
     uint32_t win_shift = 14, win_tiles = 511;
+    // blocked int8 form (pure pair energies, N >= kBlkBits): key scale
+    // 2^blk_shift, windows of blk_win_tiles tiles, stage-one weight blk_coef
+    bool blk_ok = false;
+    uint32_t blk_shift = 0, blk_win_tiles = 0;
+    int32_t blk_coef = 0;
     std::vector<uint8_t> walks;       // n_conf * N canonical site sequences, ascending
     std::vector<uint16_t> c2q;        // conformation -> class
     std::vector<uint32_t> rev_conf;   // conformation of the reversed chain
@@ -55,6 +64,7 @@ struct hp_structs {
     std::vector<uint8_t> contacts;    // n_conf * nbp * 2, (i, j) ascending
     std::vector<uint32_t> masks;      // n_conf * W contact bitmasks
     std::vector<int8_t> gemm_a;       // int8 contact matrix in MFMA A-operand order
+    std::vector<int8_t> gemm_b;       // blocked form: 0/1 contact matrix + window index rows
     std::vector<uint8_t> pair_rows;   // K_pad * 4: (i, j, constant, 0) per product row
     hpmap::WsLayout ws;
 };

@@ -14,6 +14,7 @@ struct EnumJob {
     const uint8_t *pairs;           // K_pad x 4 row table (i, j, constant, 0)
     const uint32_t *masks;          // n_conf x W contact bitmasks
     const int8_t *gemm_a;           // int8 contact matrix, MFMA A-operand order
+    const int8_t *gemm_b;           // blocked form: 0/1 contacts + window index rows
     uint16_t *out;                  // phenotype per sequence, or null
     int32_t *emin;                  // ground-state energy per sequence, or null
     unsigned long long *desig;      // designability, += (or null)
@@ -25,9 +26,20 @@ struct EnumJob {
     int32_t win_tiles, win_shift;   // int8-form key windows
     int32_t A, B, e0;               // F = A n + B u, E = e0 - F
     int32_t planes, uw, MW;         // popcount form: unary bit planes, words, mask stride
-    int32_t sym;                    // 1: [lo, hi) indexes canonical sequences (s <= rev s)
+    int32_t mode;                   // how [lo, hi) maps to sequences (SeqMode)
     int32_t half_bits;              // floor(N / 2)
+    int32_t threshold;              // folds iff second-lowest - lowest energy >= threshold
+    uint8_t *gap;                   // energy gap per sequence (saturated at 255), or null
+    uint64_t *seqs;                 // sampled mode: the sequence drawn at each index, or null
+    uint64_t seed;                  // sampled mode: generator seed
+    int32_t blk_shift, blk_win_tiles, blk_coef;   // blocked form: key scale, windows, m2 A
 };
+
+// Index -> sequence maps of a job.  kSeqPlain: index t is sequence t.
+// kSeqCanonical: t ranks the canonical sequences s <= reverse(s) (results are
+// written at s and reverse(s)).  kSeqSampled: t is a draw of the random
+// generator (results are written at t - lo).
+enum SeqMode { kSeqPlain = 0, kSeqCanonical = 1, kSeqSampled = 2 };
 
 // Work list of a batched launch, laid out in the batch workspace.
 struct BatchHeader {
@@ -55,6 +67,8 @@ int gemm_variants_kb11_12(const GemmVariant **out);
 const GemmVariant *gemm_selected_variant(int KB);
 
 hipError_t launch_popcount(const EnumJob &j, hipStream_t st);
+// Block-factorised int8 form over a plain range (pure pair energies).
+hipError_t launch_gemm_blocked(const EnumJob &j, hipStream_t st);
 // Sequences per work item of the persistent batched kernel for a given
 // deepest job (its tile shape is fixed per depth class).
 uint64_t gemm_batch_seqs_per_item(int kb_max);

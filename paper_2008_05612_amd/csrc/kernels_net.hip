@@ -16,8 +16,9 @@ namespace {
 unsigned grid_for(uint64_t n, unsigned block)
 {
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;   // a grid-size hint only
     const uint64_t want = (n + block - 1) / block;
     const uint64_t cap = uint64_t(cus) * 16;
     return unsigned(std::max<uint64_t>(1, std::min(want, cap)));

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_popcount(EnumJob j, const uint32_t *__r
             n0 = j.A * n0 + j.B * unary_sum(m + W, j.planes, j.uw, s_lo, s_hi);
         top2_add1(best, second, (n0 << kKeyConfBits) | (c + 1));
     }
-    finish_sequence(j, s, rs, valid, best, second, (threadIdx.x & 63) == 0, UN ? 1 : j.A);
+    finish_sequence(j, idx, s, rs, valid, best, second, (threadIdx.x & 63) == 0, UN ? 1 : j.A);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n)

@@ -480,6 +480,49 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
         a_byte(c, s->K + s->U + 1) = static_cast<int8_t>(-static_cast<int>(idx1 >> 7));
     }
 
+    // ---- blocked int8 form ----------------------------------------------------
+    // For a block of sequences sharing every monomer above the low kBlkBits,
+    // F = base + sum_{v low} h_v w_v + sum_{low-low pairs} A C_vv' h_v h_v'
+    // (base: pairs above the low bits; w_v: pairs of v with a monomer above).
+    // Stage one multiplies block-dependent weights into this 0/1 contact
+    // matrix to produce, per conformation, the int8 bytes -m2 base, -m2 w_v,
+    // -m2 A C_vv' and the two window index bytes; stage two multiplies them
+    // with the per-sequence indicators -128 (1, h_v, h_v h_v') and (1, -128),
+    // giving the key 128 m2 F + u.  m2 is the largest power of two with
+    // m2 A nbp <= 128, so every byte stays in range.
+    s->blk_ok = false;
+    s->gemm_b.clear();
+    if (s->U == 0 && N >= kBlkBits && A * int64_t(s->nbp) <= 128 && s->nbp > 0) {
+        int m2 = 1;
+        while (2 * m2 * A * int64_t(s->nbp) <= 128 && m2 < 64)
+            m2 *= 2;
+        int bshift = 7;
+        while ((1 << bshift) < 128 * m2)
+            ++bshift;
+        s->blk_ok = true;
+        s->blk_shift = uint32_t(bshift);
+        s->blk_win_tiles = uint32_t(((1 << bshift) - 1) / kTileConf);
+        s->blk_coef = int32_t(m2 * A);
+        const uint32_t bconf = s->blk_win_tiles * kTileConf;
+        s->gemm_b.assign(s->gemm_a.size(), 0);
+        auto b_byte = [&](uint32_t c, uint32_t k) -> int8_t & {
+            uint32_t t = c / kTileConf, col = c % kTileConf;
+            uint32_t kb = k / 32, kk = k % 32;
+            uint32_t lane = col + 32 * (kk / 16);
+            return s->gemm_b[((size_t(t) * KB + kb) * 64 + lane) * 16 + kk % 16];
+        };
+        for (uint32_t c = 0; c < n_conf; ++c) {
+            for (uint32_t q = 0; q < s->nbp; ++q) {
+                const int i = s->contacts[(size_t(c) * s->nbp + q) * 2];
+                const int j = s->contacts[(size_t(c) * s->nbp + q) * 2 + 1];
+                b_byte(c, pidx[size_t(i) * N + j]) = 1;
+            }
+            const uint32_t u = c % bconf + 1;
+            b_byte(c, s->K) = static_cast<int8_t>(u & 127);
+            b_byte(c, s->K + 1) = static_cast<int8_t>(u >> 7);
+        }
+    }
+
     // pair table for the popcount form, 4 bytes per row (i, j, 0, 0)
     s->pair_rows.assign(size_t(s->K_pad) * 4, 0);
     for (uint32_t k = 0; k < s->K_pad; ++k) {
@@ -495,7 +538,8 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
     L.pairs = up(L.c2q + size_t(n_conf) * 2);
     L.masks = up(L.pairs + s->pair_rows.size());
     L.gemm_a = up(L.masks + s->masks.size() * 4);
-    L.total = up(L.gemm_a + s->gemm_a.size());
+    L.gemm_b = up(L.gemm_a + s->gemm_a.size());
+    L.total = up(L.gemm_b + s->gemm_b.size());
     return HP_OK;
 }
 

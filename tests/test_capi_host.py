@@ -121,6 +121,29 @@ def test_argument_errors(lib):
     assert lib.hp_components(s.handle, fake_ws, None, None, None, None, None) == -1
     big = hp.Structures(6, 6, 1)
     assert lib.hp_components(big.handle, fake_ws, fake_ws, fake_ws, None, None, None) == -4
+    # energy-gap threshold outside 1 .. 255; sampling: empty draw range, idx_hi > 2^48
+    assert lib.hp_enumerate_gap(s.handle, fake_ws, 1, 0, 16, 0, None, None, None, None, None,
+                                None) == -1
+    assert lib.hp_enumerate_gap(s.handle, fake_ws, 1, 0, 16, 256, None, None, None, None, None,
+                                None) == -1
+    assert lib.hp_sample(s.handle, fake_ws, 1, 5, 9, 9, 1, None, None, None, None, None, None,
+                         None) == -1
+    assert lib.hp_sample(s.handle, fake_ws, 1, 5, 0, (1 << 48) + 1, 1, None, None, None, None,
+                         None, None, None) == -1
+    assert lib.hp_sample(s.handle, fake_ws, 1, 5, 0, 16, 0, None, None, None, None, None, None,
+                         None) == -1
+    assert lib.hp_sample(s.handle, fake_ws, 9, 5, 0, 16, 1, None, None, None, None, None, None,
+                         None) == -1
+    # blocked form: plain ranges of pure pair energies with N >= 8 only
+    assert lib.hp_enumerate_symmetric(s.handle, fake_ws, 2, 0, 16, None, None, None, None,
+                                      None) == -5
+    assert lib.hp_sample(s.handle, fake_ws, 2, 5, 0, 16, 1, None, None, None, None, None, None,
+                         None) == -5
+    tiny = hp.Structures(2, 3, 1)
+    assert lib.hp_enumerate(tiny.handle, fake_ws, 2, 0, 16, None, None, None, None, None) == -5
+    t96 = hp.Structures(4, 4, 1, table=(0, -10, -10, -23))
+    assert lib.hp_enumerate(t96.handle, fake_ws, 2, 0, 16, None, None, None, None, None) == -5
+    assert lib.hp_enumerate(s.handle, fake_ws, 3, 0, 16, None, None, None, None, None) == -1
     assert lib.hp_upload(s.handle, fake_ws, 10, None) == -1
     assert lib.hp_upload(s.handle, ctypes.c_void_p(257), 1 << 30, None) == -1
     assert lib.hp_batch_workspace_bytes(0) == 0
