@@ -2,14 +2,21 @@
 """Benchmark of the HP genotype-phenotype map hot path on one MI355X.
 
 One step = the whole path over the 3x3x3 cube: ground states of all 2^27
-sequences against all 103346 conformations (int8-MFMA form: energy GEMM,
-min/unique/argmin epilogue, designability atomics), then the single-mutation
-neighbour counts (with the phi row of the most designable phenotype) and the
-neutral-network union-find over the full map.  Structures are enumerated and
-uploaded once before timing; all inputs are resident in HBM.
+sequences against all 103346 conformations (block-factorised int8-MFMA form:
+energy products, min/unique/argmin epilogue, designability atomics), then the
+single-mutation neighbour counts (with the phi row of the most designable
+phenotype) and the neutral-network union-find over the full map.  Structures
+are enumerated and uploaded once before timing; all inputs are resident in
+HBM.
 
-Prints ONE JSON line.  Extra measurements (popcount form on a slice, a 6x6
-block, per-kernel times) go in the same line under "extra".
+The dominant kernel is bound by its vector-ALU epilogue (the running top-2
+of the keys, 1.25 VALU operations per sequence-conformation pair), so its
+roofline is the 32-bit VALU peak; the dense int8 form's fraction of the int8
+MFMA peak and the popcount form are measured on the same GPU under "extra".
+
+Prints ONE JSON line.  Extra measurements (dense int8 and popcount forms, a
+6x6 block in all forms, the sampling mode, per-kernel times) go in the same
+line under "extra".
 """
 from __future__ import annotations
 
@@ -26,6 +33,7 @@ METRIC = ("seq×structure evals/s + full-map wall time (3×3×3, 6×6); "
           "% int8 MFMA peak")
 PEAK_INT8_TOPS = 5000.0          # MI355X dense int8 MFMA, TOP/s
 PEAK_VALU_TOPS = 256 * 2.4e9 * 64 / 1e12   # 32-bit VALU lane-ops/s: 256 CU x 64 lanes/clk x 2.4 GHz
+EPILOGUE_OPS_PER_PAIR = 1.25     # v_med3 + v_max3 per two keys, one v_max3 per four
 
 
 def parse():
@@ -37,9 +45,10 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true",
-                    help="time every compiled tile shape first and use the fastest "
-                         "(default: the library's default shape, whose HBM counters are "
-                         "recorded under profiles/)")
+                    help="time every compiled tile shape of the dense int8 form first and "
+                         "use the fastest for its extra measurement")
+    ap.add_argument("--nw", type=int, default=4,
+                    help="waves per workgroup of the blocked form (2, 4 or 8)")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: no extras, no CPU baseline, plus a 256 MiB device "
                          "copy used to calibrate the HBM byte counters")
@@ -91,9 +100,8 @@ def main():
     tune_ms = None
     if args.autotune:
         _, tune_ms = hp.hp_autotune(s, ws, 0, 1 << 20, repeats=2)
-    shape_idx = hp.hp_gemm_selected(s.K_pad)
-    T, NW, mode = hp.hp_gemm_shapes(s.K_pad)[shape_idx]
-    kname = "k_gemm<%d,%d,%d,%d>" % (s.K_pad // 32, T, NW, mode)
+    hp.hp_blocked_select(args.nw)
+    kname = "k_gemm_blk<%d,%d>" % (s.K_pad // 32, args.nw)
     pairs = total * n_conf
 
     out = torch.empty(total, dtype=torch.int16, device=dev)
@@ -114,7 +122,7 @@ def main():
         for t in (desig, nond, neu, dele, oth, row):
             t.zero_()
         timers["enumerate"].start()
-        hp.hp_enumerate(s, ws, hp.FORM_GEMM_I8, 0, total, out, None, desig, nond)
+        hp.hp_enumerate(s, ws, hp.FORM_BLOCKED_I8, 0, total, out, None, desig, nond)
         timers["enumerate"].stop()
         timers["neighbors"].start()
         hp.hp_neighbors(s, out, neu, dele, oth, phi_q, row if phi_q >= 0 else None)
@@ -143,9 +151,12 @@ def main():
     assert int(d.sum()) + nd == total, "designability + deleterious != 2^N"
 
     enum_ms = float(np.mean(kms["enumerate"]))
-    algo_ops = 2.0 * s.K * pairs                      # dense GEMM over the K pair rows
-    issued_ops = 2.0 * s.K_pad * pairs                # what the MFMA pipe executes
-    achieved_tops = algo_ops / (enum_ms * 1e-3) / 1e12
+    alu_ops = EPILOGUE_OPS_PER_PAIR * pairs           # top-2 key updates
+    achieved_tops = alu_ops / (enum_ms * 1e-3) / 1e12
+    # MFMA work the blocked form issues: one depth-32 product per pair, plus
+    # the per-block stage (K_pad deep, 32 virtual rows) per conformation tile
+    n_tiles = (n_conf + 31) // 32
+    blk_mfma_ops = 2.0 * 32 * pairs + 2.0 * s.K_pad * 32 * 32 * n_tiles * (total // 256)
     evals_per_s = pairs / (ms_step * 1e-3)
 
     result = {
@@ -163,27 +174,29 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "3x3x3 full map: all 2^27 sequences x 103346 conformations "
-                        "(int8-MFMA form) + single-mutation neighbour counts + union-find",
+                        "(block-factorised int8-MFMA form) + single-mutation neighbour "
+                        "counts + union-find",
             "lattice": "3x3x3", "N": N, "sequences": total, "n_conf": n_conf,
-            "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "form": "gemm_i8",
-            "tile_shape": {"T": T, "NW": NW, "mode": "lds" if mode == 0 else "direct"},
+            "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "form": "blocked_i8",
+            "waves_per_workgroup": args.nw,
         },
         "roofline": {
-            "bound": "mfma",
+            "bound": "alu",
             "achieved": achieved_tops,
-            "peak": PEAK_INT8_TOPS,
+            "peak": PEAK_VALU_TOPS,
             "unit": "TOP/s",
-            "frac": achieved_tops / PEAK_INT8_TOPS,
+            "frac": achieved_tops / PEAK_VALU_TOPS,
             "traffic": recorded_traffic(kname),
-            "kernel": kname + " (hp_enumerate, int8 MFMA)",
-            "ops_per_unit": 2 * s.K,
+            "kernel": kname + " (hp_enumerate, blocked int8 form)",
+            "ops_per_unit": EPILOGUE_OPS_PER_PAIR,
         },
     }
     extra = {
         "full_map_ms_3x3x3": ms_step,
         "kernel_ms": {k: float(np.mean(v)) for k, v in kms.items()},
         "enumerate_evals_per_s": pairs / (enum_ms * 1e-3),
-        "mfma_issued_frac": issued_ops / (enum_ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
+        "blocked_mfma_issued_frac": blk_mfma_ops / (enum_ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
+        "blocked_dense_equivalent_int8_tops": 2.0 * s.K * pairs / (enum_ms * 1e-3) / 1e12,
         "designing_fraction": float(d.sum()) / total,
         "top_class": top,
         "top_designability": int(d[top]),
@@ -191,7 +204,7 @@ def main():
         "autotune_ms_per_shape": tune_ms,
     }
     if not args.no_extra:
-        extra.update(extra_measurements(hp, s, ws, dev))
+        extra.update(extra_measurements(hp, s, ws, dev, out))
     if args.profile:
         # a plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters
         a = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
@@ -209,9 +222,9 @@ def main():
 
 def recorded_traffic(kname):
     """HBM bytes per full-map launch of `kname`, from the calibrated
-    FETCH_SIZE / WRITE_SIZE counter summary in profiles/, or None when that
-    summary is for another kernel."""
-    path = os.path.join(ROOT, "profiles", "k_gemm_3x3x3_hbm_traffic.txt")
+    FETCH_SIZE / WRITE_SIZE counter summary of the blocked kernel in
+    profiles/, or None when that summary is for another kernel."""
+    path = os.path.join(ROOT, "profiles", "k_gemm_blk_3x3x3_hbm_traffic.txt")
     try:
         fields = {}
         for line in open(path):
@@ -225,15 +238,35 @@ def recorded_traffic(kname):
         return None
 
 
-def extra_measurements(hp, s, ws, dev):
-    """Popcount form on a 2^24 slice of the cube (same GPU), the sampling mode
-    on both lattices, and one 2^28 block of the 6x6 map in both forms, with the
-    full 6x6 time extrapolated."""
+def extra_measurements(hp, s, ws, dev, blocked_map):
+    """The dense int8 form over the same full 3x3x3 map (its fraction of the
+    int8 MFMA peak, and a bit-exact comparison with the blocked form's map),
+    the popcount form on a 2^24 slice, the sampling mode on both lattices, and
+    one 2^28 block of the 6x6 map in all three forms with the full 6x6 time
+    extrapolated."""
     import torch
     res = {}
-    n = 1 << 24
     t = Timer()
-    for form, name in ((hp.FORM_POPCOUNT, "popcount"), (hp.FORM_GEMM_I8, "gemm_i8")):
+    total = 1 << s.N
+    dense = torch.empty(total, dtype=torch.int16, device=dev)
+    hp.hp_enumerate(s, ws, hp.FORM_GEMM_I8, 0, 1 << 16, dense)
+    torch.cuda.synchronize()
+    t.start()
+    hp.hp_enumerate(s, ws, hp.FORM_GEMM_I8, 0, total, dense)
+    t.stop()
+    torch.cuda.synchronize()
+    T, NW, mode = hp.hp_gemm_shapes(s.K_pad)[hp.hp_gemm_selected(s.K_pad)]
+    res["dense_gemm_i8_shape"] = {"T": T, "NW": NW, "mode": mode}
+    res["dense_gemm_i8_full_map_ms_3x3x3"] = t.ms()
+    res["dense_gemm_i8_evals_per_s"] = total * s.n_conf / (t.ms() * 1e-3)
+    res["dense_gemm_i8_mfma_frac"] = (2.0 * s.K * total * s.n_conf / (t.ms() * 1e-3) / 1e12 /
+                                      PEAK_INT8_TOPS)
+    res["dense_gemm_i8_mfma_issued_frac"] = (2.0 * s.K_pad * total * s.n_conf /
+                                             (t.ms() * 1e-3) / 1e12 / PEAK_INT8_TOPS)
+    res["blocked_map_equals_dense_map"] = bool(torch.equal(dense, blocked_map))
+    del dense
+    n = 1 << 24
+    for form, name in ((hp.FORM_POPCOUNT, "popcount"), (hp.FORM_BLOCKED_I8, "blocked_i8")):
         hp.hp_enumerate(s, ws, form, 0, 1 << 16)
         torch.cuda.synchronize()
         t.start()
@@ -241,8 +274,10 @@ def extra_measurements(hp, s, ws, dev):
         t.stop()
         torch.cuda.synchronize()
         res["3x3x3_slice_%s_evals_per_s" % name] = n * s.n_conf / (t.ms() * 1e-3)
-    res["gemm_over_popcount_3x3x3"] = (res["3x3x3_slice_gemm_i8_evals_per_s"] /
-                                       res["3x3x3_slice_popcount_evals_per_s"])
+    res["blocked_over_popcount_3x3x3"] = (res["3x3x3_slice_blocked_i8_evals_per_s"] /
+                                          res["3x3x3_slice_popcount_evals_per_s"])
+    res["dense_over_popcount_3x3x3"] = (res["dense_gemm_i8_evals_per_s"] /
+                                        res["3x3x3_slice_popcount_evals_per_s"])
     # the popcount loop issues 2W + 4 VALU instructions per pair (W ANDs, W
     # bit counts, 4 for the key and top-2 update)
     res["popcount_valu_frac_3x3x3"] = (res["3x3x3_slice_popcount_evals_per_s"] *
@@ -272,19 +307,21 @@ def extra_measurements(hp, s, ws, dev):
     res["6x6_sample_2^22_s_per_sequence"] = t.ms() * 1e-3 / (1 << 22)
     n6 = 1 << 28
     d6 = torch.zeros(s6.n_class, dtype=torch.int64, device=dev)
-    for form, name in ((hp.FORM_GEMM_I8, "gemm_i8"), (hp.FORM_POPCOUNT, "popcount")):
+    for form, name, nn in ((hp.FORM_BLOCKED_I8, "blocked_i8", n6), (hp.FORM_GEMM_I8, "gemm_i8", n6),
+                           (hp.FORM_POPCOUNT, "popcount", n6 // 4)):
         hp.hp_enumerate(s6, ws6, form, 0, 1 << 16, None, None, d6)
         torch.cuda.synchronize()
         t.start()
-        hp.hp_enumerate(s6, ws6, form, 0, n6 if name == "gemm_i8" else n6 // 4, None, None, d6)
+        hp.hp_enumerate(s6, ws6, form, 0, nn, None, None, d6)
         t.stop()
         torch.cuda.synchronize()
-        nn = n6 if name == "gemm_i8" else n6 // 4
         rate = nn * s6.n_conf / (t.ms() * 1e-3)
         res["6x6_block_%s_evals_per_s" % name] = rate
         res["6x6_full_map_s_extrapolated_%s" % name] = (1 << 36) * s6.n_conf / rate
     res["6x6_gemm_i8_mfma_frac"] = (res["6x6_block_gemm_i8_evals_per_s"] * 2 * s6.K /
                                     (PEAK_INT8_TOPS * 1e12))
+    res["6x6_blocked_valu_frac"] = (res["6x6_block_blocked_i8_evals_per_s"] *
+                                    EPILOGUE_OPS_PER_PAIR / (PEAK_VALU_TOPS * 1e12))
     return res
 
 

@@ -263,11 +263,23 @@ hp_status hp_graph_launch(hp_graph *g, void *stream);
 void hp_graph_free(hp_graph *g);
 
 /*
+ * Launch shape of HP_FORM_BLOCKED_I8: every wave scores one block of 256
+ * sequences; hp_blocked_select sets the waves per workgroup (2, 4 or 8;
+ * default 4; the waves of a workgroup share each staged contact tile), a
+ * process-wide choice.  hp_blocked_selected returns it.
+ * Errors: HP_EINVAL for another value.
+ */
+hp_status hp_blocked_select(int nw);
+int hp_blocked_selected(void);
+
+/*
  * Tile shapes of the int8 form and their autotuning.  Several shapes are
  * compiled per product depth K_pad (hp_info.K_pad).  A shape is (T, NW, mode):
  * T sequence tiles of 32 per wave, NW waves per workgroup, and mode 0 when
- * the contact-matrix tiles are staged through LDS by the workgroup or 1 when
- * every wave loads them from global memory itself.  The choice is
+ * the contact-matrix tiles are staged through LDS by the workgroup, 1 when
+ * every wave loads them from global memory itself, 2 when they are staged
+ * through LDS and each wave overlaps the products of one tile with the key
+ * updates of the previous one.  The choice is
  * process-wide per K_pad and shared by all threads; the first listed shape is
  * the default.  The launch configuration never changes results, only speed.
  *   hp_gemm_shape_count  number of compiled shapes for K_pad (0 if none);

@@ -18,6 +18,8 @@ from ._binding import (  # noqa: F401
     hp_components,
     hp_enumerate,
     hp_autotune,
+    hp_blocked_select,
+    hp_blocked_selected,
     hp_canonical_count,
     hp_enumerate_batch,
     hp_enumerate_gap,

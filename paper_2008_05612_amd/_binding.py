@@ -91,6 +91,8 @@ def library():
         "hp_graph_free": (None, [vp]),
         "hp_neighbors": (st, [vp, vp, vp, vp, vp, i32, vp, vp]),
         "hp_components": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "hp_blocked_select": (st, [ctypes.c_int]),
+        "hp_blocked_selected": (ctypes.c_int, []),
         "hp_gemm_shape_count": (ctypes.c_int, [ctypes.c_uint32]),
         "hp_gemm_shape_info": (st, [ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -265,6 +267,15 @@ def hp_sample(s: Structures, ws, form: int, seed: int, idx_lo: int, idx_hi: int,
         _ptr(emin, torch.int32, n, "emin"), _ptr(gap, torch.uint8, n, "gap"),
         _ptr(designability, torch.int64, s.n_class, "designability"),
         _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)), "hp_sample")
+
+
+def hp_blocked_select(nw: int):
+    """Waves per workgroup of the blocked int8 form (2, 4 or 8)."""
+    _check(library().hp_blocked_select(nw), "hp_blocked_select")
+
+
+def hp_blocked_selected() -> int:
+    return int(library().hp_blocked_selected())
 
 
 def hp_canonical_count(s: Structures) -> int:

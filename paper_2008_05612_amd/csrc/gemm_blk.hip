@@ -128,11 +128,14 @@ __device__ __forceinline__ void blk_s_fragments(int col, int half, v4i (&sf)[kBl
     }
 }
 
-// Low bytes of four int32 values (each in [-128, 127]) packed little-endian.
+// Low bytes of four int32 values (each in [-128, 127]) packed little-endian,
+// three byte permutes: v_perm_b32(x, y, sel) picks result byte i as byte
+// sel_i of the 8-byte value {x (bytes 4..7), y (bytes 0..3)}; 0x0c gives 0.
 __device__ __forceinline__ int pack4(int a, int b, int c, int d)
 {
-    return int((uint32_t(a) & 0xffu) | ((uint32_t(b) & 0xffu) << 8) |
-               ((uint32_t(c) & 0xffu) << 16) | (uint32_t(d) << 24));
+    const uint32_t ab = __builtin_amdgcn_perm(uint32_t(b), uint32_t(a), 0x0c0c0400u);
+    const uint32_t cd = __builtin_amdgcn_perm(uint32_t(d), uint32_t(c), 0x0c0c0400u);
+    return int(__builtin_amdgcn_perm(cd, ab, 0x05040100u));
 }
 
 // One wave scores one block of 256 sequences against every conformation
@@ -214,10 +217,9 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
     }
 }
 
-template <int KB>
-hipError_t launch_blk(const EnumJob &j, hipStream_t st)
+template <int KB, int NW>
+hipError_t launch_blk_nw(const EnumJob &j, hipStream_t st)
 {
-    constexpr int NW = 4;
     const uint64_t first = j.lo >> kBlkBits, last = (j.hi - 1) >> kBlkBits;
     const uint64_t n_blocks = last - first + 1;
     const dim3 grid(unsigned((n_blocks + NW - 1) / NW));
@@ -225,23 +227,33 @@ hipError_t launch_blk(const EnumJob &j, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int KB>
+hipError_t launch_blk(const EnumJob &j, int nw, hipStream_t st)
+{
+    switch (nw) {
+    case 2: return launch_blk_nw<KB, 2>(j, st);
+    case 8: return launch_blk_nw<KB, 8>(j, st);
+    default: return launch_blk_nw<KB, 4>(j, st);
+    }
+}
+
 }  // namespace
 
-hipError_t launch_gemm_blocked(const EnumJob &j, hipStream_t st)
+hipError_t launch_gemm_blocked(const EnumJob &j, int nw, hipStream_t st)
 {
     switch (j.KB) {
-    case 1: return launch_blk<1>(j, st);
-    case 2: return launch_blk<2>(j, st);
-    case 3: return launch_blk<3>(j, st);
-    case 4: return launch_blk<4>(j, st);
-    case 5: return launch_blk<5>(j, st);
-    case 6: return launch_blk<6>(j, st);
-    case 7: return launch_blk<7>(j, st);
-    case 8: return launch_blk<8>(j, st);
-    case 9: return launch_blk<9>(j, st);
-    case 10: return launch_blk<10>(j, st);
-    case 11: return launch_blk<11>(j, st);
-    case 12: return launch_blk<12>(j, st);
+    case 1: return launch_blk<1>(j, nw, st);
+    case 2: return launch_blk<2>(j, nw, st);
+    case 3: return launch_blk<3>(j, nw, st);
+    case 4: return launch_blk<4>(j, nw, st);
+    case 5: return launch_blk<5>(j, nw, st);
+    case 6: return launch_blk<6>(j, nw, st);
+    case 7: return launch_blk<7>(j, nw, st);
+    case 8: return launch_blk<8>(j, nw, st);
+    case 9: return launch_blk<9>(j, nw, st);
+    case 10: return launch_blk<10>(j, nw, st);
+    case 11: return launch_blk<11>(j, nw, st);
+    case 12: return launch_blk<12>(j, nw, st);
     default: return hipErrorInvalidValue;
     }
 }

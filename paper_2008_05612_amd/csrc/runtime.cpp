@@ -1,6 +1,7 @@
 // Runtime pieces of libhpmap around the int8 kernels: the registry of compiled
-// tile shapes, the process-wide shape choice per product depth, the
-// autotuner that times the shapes on the device, and its on-disk cache.
+// tile shapes, the process-wide shape choice per product depth (and the
+// blocked form's waves per workgroup), the autotuner that times the shapes
+// on the device, and its on-disk cache.
 //
 // Cache file (path in the HP_TUNE_CACHE environment variable, optional): one
 // line per depth, "gfx950 <K_pad> <T> <NW> <mode>", written by hp_autotune and
@@ -125,11 +126,27 @@ const GemmVariant *gemm_selected_variant(int KB)
     return &v[idx];
 }
 
+namespace {
+std::atomic<int> g_blocked_nw{4};   // waves per workgroup of the blocked form
+}
+
+int blocked_selected_nw() { return g_blocked_nw.load(); }
+
 }  // namespace hpmap
 
 using namespace hpmap;
 
 extern "C" {
+
+hp_status hp_blocked_select(int nw)
+{
+    if (nw != 2 && nw != 4 && nw != 8)
+        return fail(HP_EINVAL, "blocked form: waves per workgroup must be 2, 4 or 8");
+    g_blocked_nw.store(nw);
+    return HP_OK;
+}
+
+int hp_blocked_selected(void) { return g_blocked_nw.load(); }
 
 int hp_gemm_shape_count(uint32_t K_pad)
 {
