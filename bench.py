@@ -49,6 +49,8 @@ def parse():
                          "use the fastest for its extra measurement")
     ap.add_argument("--nw", type=int, default=4,
                     help="waves per workgroup of the blocked form (2, 4 or 8)")
+    ap.add_argument("--blk-mode", type=int, default=0,
+                    help="staging mode of the blocked form (0 double-buffered, 1 pipelined)")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: no extras, no CPU baseline, plus a 256 MiB device "
                          "copy used to calibrate the HBM byte counters")
@@ -100,8 +102,8 @@ def main():
     tune_ms = None
     if args.autotune:
         _, tune_ms = hp.hp_autotune(s, ws, 0, 1 << 20, repeats=2)
-    hp.hp_blocked_select(args.nw)
-    kname = "k_gemm_blk<%d,%d>" % (s.K_pad // 32, args.nw)
+    hp.hp_blocked_select(args.nw, args.blk_mode)
+    kname = "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, args.nw, args.blk_mode)
     pairs = total * n_conf
 
     out = torch.empty(total, dtype=torch.int16, device=dev)
@@ -178,7 +180,7 @@ def main():
                         "counts + union-find",
             "lattice": "3x3x3", "N": N, "sequences": total, "n_conf": n_conf,
             "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "form": "blocked_i8",
-            "waves_per_workgroup": args.nw,
+            "waves_per_workgroup": args.nw, "staging_mode": args.blk_mode,
         },
         "roofline": {
             "bound": "alu",

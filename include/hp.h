@@ -264,13 +264,16 @@ void hp_graph_free(hp_graph *g);
 
 /*
  * Launch shape of HP_FORM_BLOCKED_I8: every wave scores one block of 256
- * sequences; hp_blocked_select sets the waves per workgroup (2, 4 or 8;
- * default 4; the waves of a workgroup share each staged contact tile), a
- * process-wide choice.  hp_blocked_selected returns it.
+ * sequences.  hp_blocked_select sets, process-wide, the waves per workgroup
+ * nw (2, 4 or 8; default 4; the waves of a workgroup share each staged
+ * contact tile) and the staging mode (0, default: double-buffered LDS; 1:
+ * triple-buffered LDS with the block-level product of the next tile issued
+ * while the current tile's keys are updated).  hp_blocked_selected reports
+ * them (either pointer may be NULL).  Results never depend on the shape.
  * Errors: HP_EINVAL for another value.
  */
-hp_status hp_blocked_select(int nw);
-int hp_blocked_selected(void);
+hp_status hp_blocked_select(int nw, int mode);
+void hp_blocked_selected(int *nw, int *mode);
 
 /*
  * Tile shapes of the int8 form and their autotuning.  Several shapes are

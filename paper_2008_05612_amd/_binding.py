@@ -91,8 +91,8 @@ def library():
         "hp_graph_free": (None, [vp]),
         "hp_neighbors": (st, [vp, vp, vp, vp, vp, i32, vp, vp]),
         "hp_components": (st, [vp, vp, vp, vp, vp, vp, vp]),
-        "hp_blocked_select": (st, [ctypes.c_int]),
-        "hp_blocked_selected": (ctypes.c_int, []),
+        "hp_blocked_select": (st, [ctypes.c_int, ctypes.c_int]),
+        "hp_blocked_selected": (None, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "hp_gemm_shape_count": (ctypes.c_int, [ctypes.c_uint32]),
         "hp_gemm_shape_info": (st, [ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -269,13 +269,17 @@ def hp_sample(s: Structures, ws, form: int, seed: int, idx_lo: int, idx_hi: int,
         _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)), "hp_sample")
 
 
-def hp_blocked_select(nw: int):
-    """Waves per workgroup of the blocked int8 form (2, 4 or 8)."""
-    _check(library().hp_blocked_select(nw), "hp_blocked_select")
+def hp_blocked_select(nw: int, mode: int = 0):
+    """Launch shape of the blocked int8 form: waves per workgroup (2, 4 or 8)
+    and staging mode (0 double-buffered, 1 pipelined)."""
+    _check(library().hp_blocked_select(nw, mode), "hp_blocked_select")
 
 
-def hp_blocked_selected() -> int:
-    return int(library().hp_blocked_selected())
+def hp_blocked_selected():
+    """(nw, mode) of the blocked int8 form."""
+    nw, mode = ctypes.c_int(), ctypes.c_int()
+    library().hp_blocked_selected(ctypes.byref(nw), ctypes.byref(mode))
+    return nw.value, mode.value
 
 
 def hp_canonical_count(s: Structures) -> int:

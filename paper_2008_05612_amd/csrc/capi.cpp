@@ -302,7 +302,7 @@ hp_status run_blocks(const hp_structs *s, const void *d_ws, int form, uint64_t l
         j.gap = o.gap && local ? o.gap + off : o.gap;
         j.seqs = o.seqs ? o.seqs + off : nullptr;
         hipError_t e = form == HP_FORM_POPCOUNT ? launch_popcount(j, hs)
-                       : form == HP_FORM_BLOCKED_I8 ? launch_gemm_blocked(j, blocked_selected_nw(), hs)
+                       : form == HP_FORM_BLOCKED_I8 ? launch_gemm_blocked(j, blocked_selected_nw(), blocked_selected_mode(), hs)
                                                     : var->launch(j, hs);
         if (e != hipSuccess)
             return device_fail(e, what);

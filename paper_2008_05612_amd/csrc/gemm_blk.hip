@@ -138,13 +138,60 @@ __device__ __forceinline__ int pack4(int a, int b, int c, int d)
     return int(__builtin_amdgcn_perm(cd, ab, 0x05040100u));
 }
 
+template <int KB>
+__device__ __forceinline__ v16i stage_one(const v4i (&vf)[KB], const v4i *tile, int lane)
+{
+    v16i d1;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const v16i zero = {};
+        d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(vf[kb], tile[kb * 64 + lane],
+                                                   kb == 0 ? zero : d1, 0, 0, 0);
+    }
+    return d1;
+}
+
+__device__ __forceinline__ v4i pack_d1(const v16i &d1)
+{
+    return v4i{pack4(d1[0], d1[1], d1[2], d1[3]), pack4(d1[4], d1[5], d1[6], d1[7]),
+               pack4(d1[8], d1[9], d1[10], d1[11]), pack4(d1[12], d1[13], d1[14], d1[15])};
+}
+
+// Stage two of one conformation tile for the wave's 8 sequence tiles, with
+// the top-2 key update of each result.  The product of sequence tile t+1 is
+// issued before the key updates of tile t (two accumulators), so the wave
+// does not wait on each product's latency.
+__device__ __forceinline__ void stage_two(const v4i &a2, const v4i (&sf)[kBlkTiles],
+                                          int (&b)[kBlkTiles], int (&sc)[kBlkTiles])
+{
+    const v16i zero = {};
+    v16i acc[2];
+    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[0], zero, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t) {
+        if (t + 1 < kBlkTiles)
+            acc[(t + 1) & 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[t + 1], zero, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; r += 2)
+            top2_add2(b[t], sc[t], acc[t & 1][r], acc[t & 1][r + 1]);
+    }
+}
+
+// Staging of the C1 tiles:
+//   kBlkLds  : double-buffered LDS, one barrier per tile; stage one of a tile
+//              runs right before its stage two.
+//   kBlkPipe : triple-buffered LDS; the stage-one products of tile t+1 are
+//              issued during iteration t, so the matrix pipe works on them
+//              while the vector ALU runs tile t's key updates.
+enum { kBlkLds = 0, kBlkPipe = 1 };
+
 // One wave scores one block of 256 sequences against every conformation
 // tile; the NW waves of a workgroup take consecutive blocks and share the
-// C1 tiles through double-buffered LDS (one barrier per tile).
-template <int KB, int NW>
+// C1 tiles through LDS.
+template <int KB, int NW, int MODE>
 __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
 {
-    __shared__ v4i lds[2 * KB * 64];
+    __shared__ v4i lds[(MODE == kBlkPipe ? 3 : 2) * KB * 64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 31;
@@ -170,40 +217,62 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
     int conf_base = 0;
 
     TileStage<KB, NW> stg;
-    stg.load(B1, 0);
-    stg.store(lds);
-    __syncthreads();
-    for (int tile = 0; tile < n_tiles; ++tile) {
-        const bool more = tile + 1 < n_tiles;
-        if (more)
-            stg.load(B1, tile + 1);
-        const v4i *cur = lds + (tile & 1) * (KB * 64);
-        v16i d1;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            const v16i zero = {};
-            d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(vf[kb], cur[kb * 64 + lane],
-                                                       kb == 0 ? zero : d1, 0, 0, 0);
-        }
-        const v4i a2 = v4i{pack4(d1[0], d1[1], d1[2], d1[3]), pack4(d1[4], d1[5], d1[6], d1[7]),
-                           pack4(d1[8], d1[9], d1[10], d1[11]),
-                           pack4(d1[12], d1[13], d1[14], d1[15])};
-#pragma unroll
-        for (int t = 0; t < kBlkTiles; ++t) {
-            const v16i zero = {};
-            const v16i acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[t], zero, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 16; r += 2)
-                top2_add2(b[t], sc[t], acc[r], acc[r + 1]);
-        }
-        if (tile + 1 == wend) {
-            fold_window<kBlkTiles>(b, sc, gb, gs, conf_base, win_shift);
-            conf_base += win_tiles * kTileConf;
-            wend = min(wend + win_tiles, n_tiles);
-        }
-        if (more)
-            stg.store(lds + ((tile + 1) & 1) * (KB * 64));
+    constexpr int TV = KB * 64;   // vectors per staged tile
+    if constexpr (MODE == kBlkLds) {
+        stg.load(B1, 0);
+        stg.store(lds);
         __syncthreads();
+        for (int tile = 0; tile < n_tiles; ++tile) {
+            const bool more = tile + 1 < n_tiles;
+            if (more)
+                stg.load(B1, tile + 1);
+            const v16i d1 = stage_one<KB>(vf, lds + (tile & 1) * TV, lane);
+            stage_two(pack_d1(d1), sf, b, sc);
+            if (tile + 1 == wend) {
+                fold_window<kBlkTiles>(b, sc, gb, gs, conf_base, win_shift);
+                conf_base += win_tiles * kTileConf;
+                wend = min(wend + win_tiles, n_tiles);
+            }
+            if (more)
+                stg.store(lds + ((tile + 1) & 1) * TV);
+            __syncthreads();
+        }
+    } else {
+        // Buffer t % 3 holds tile t.  Iteration t: prefetch tile t+2 from
+        // global memory, pack tile t's stage-one result, issue stage one of
+        // tile t+1 (buffer (t+1) % 3) and stage two of tile t, store tile t+2
+        // into buffer (t+2) % 3 = (t-1) % 3 -- last read by stage one of tile
+        // t-1 in iteration t-2, two barriers back -- then one barrier.
+        stg.load(B1, 0);
+        stg.store(lds);
+        if (n_tiles > 1) {
+            stg.load(B1, 1);
+            stg.store(lds + TV);
+        }
+        __syncthreads();
+        v16i d1 = stage_one<KB>(vf, lds, lane);
+        int cur = 0;   // buffer of tile `tile`
+        for (int tile = 0; tile < n_tiles; ++tile) {
+            const bool has1 = tile + 1 < n_tiles;
+            const bool has2 = tile + 2 < n_tiles;
+            if (has2)
+                stg.load(B1, tile + 2);
+            const v4i a2 = pack_d1(d1);
+            const int nxt = cur == 2 ? 0 : cur + 1;
+            const int nn = nxt == 2 ? 0 : nxt + 1;
+            if (has1)
+                d1 = stage_one<KB>(vf, lds + nxt * TV, lane);
+            stage_two(a2, sf, b, sc);
+            if (tile + 1 == wend) {
+                fold_window<kBlkTiles>(b, sc, gb, gs, conf_base, win_shift);
+                conf_base += win_tiles * kTileConf;
+                wend = min(wend + win_tiles, n_tiles);
+            }
+            if (has2)
+                stg.store(lds + nn * TV);
+            __syncthreads();
+            cur = nxt;
+        }
     }
 
 #pragma unroll
@@ -217,43 +286,50 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
     }
 }
 
-template <int KB, int NW>
-hipError_t launch_blk_nw(const EnumJob &j, hipStream_t st)
+template <int KB, int NW, int MODE>
+hipError_t launch_blk_shape(const EnumJob &j, hipStream_t st)
 {
     const uint64_t first = j.lo >> kBlkBits, last = (j.hi - 1) >> kBlkBits;
     const uint64_t n_blocks = last - first + 1;
     const dim3 grid(unsigned((n_blocks + NW - 1) / NW));
-    hipLaunchKernelGGL((k_gemm_blk<KB, NW>), grid, dim3(NW * 64), 0, st, j);
+    hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE>), grid, dim3(NW * 64), 0, st, j);
     return hipGetLastError();
 }
 
 template <int KB>
-hipError_t launch_blk(const EnumJob &j, int nw, hipStream_t st)
+hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
 {
+    if (mode == kBlkPipe) {
+        switch (nw) {
+        case 2: return launch_blk_shape<KB, 2, kBlkPipe>(j, st);
+        case 8: return launch_blk_shape<KB, 8, kBlkPipe>(j, st);
+        default: return launch_blk_shape<KB, 4, kBlkPipe>(j, st);
+        }
+    }
     switch (nw) {
-    case 2: return launch_blk_nw<KB, 2>(j, st);
-    case 8: return launch_blk_nw<KB, 8>(j, st);
-    default: return launch_blk_nw<KB, 4>(j, st);
+    case 2: return launch_blk_shape<KB, 2, kBlkLds>(j, st);
+    case 8: return launch_blk_shape<KB, 8, kBlkLds>(j, st);
+    default: return launch_blk_shape<KB, 4, kBlkLds>(j, st);
     }
 }
 
 }  // namespace
 
-hipError_t launch_gemm_blocked(const EnumJob &j, int nw, hipStream_t st)
+hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t st)
 {
     switch (j.KB) {
-    case 1: return launch_blk<1>(j, nw, st);
-    case 2: return launch_blk<2>(j, nw, st);
-    case 3: return launch_blk<3>(j, nw, st);
-    case 4: return launch_blk<4>(j, nw, st);
-    case 5: return launch_blk<5>(j, nw, st);
-    case 6: return launch_blk<6>(j, nw, st);
-    case 7: return launch_blk<7>(j, nw, st);
-    case 8: return launch_blk<8>(j, nw, st);
-    case 9: return launch_blk<9>(j, nw, st);
-    case 10: return launch_blk<10>(j, nw, st);
-    case 11: return launch_blk<11>(j, nw, st);
-    case 12: return launch_blk<12>(j, nw, st);
+    case 1: return launch_blk<1>(j, nw, mode, st);
+    case 2: return launch_blk<2>(j, nw, mode, st);
+    case 3: return launch_blk<3>(j, nw, mode, st);
+    case 4: return launch_blk<4>(j, nw, mode, st);
+    case 5: return launch_blk<5>(j, nw, mode, st);
+    case 6: return launch_blk<6>(j, nw, mode, st);
+    case 7: return launch_blk<7>(j, nw, mode, st);
+    case 8: return launch_blk<8>(j, nw, mode, st);
+    case 9: return launch_blk<9>(j, nw, mode, st);
+    case 10: return launch_blk<10>(j, nw, mode, st);
+    case 11: return launch_blk<11>(j, nw, mode, st);
+    case 12: return launch_blk<12>(j, nw, mode, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -68,10 +68,14 @@ const GemmVariant *gemm_selected_variant(int KB);
 
 hipError_t launch_popcount(const EnumJob &j, hipStream_t st);
 // Block-factorised int8 form over a plain range (pure pair energies); nw
-// waves per workgroup (2, 4 or 8), one 256-sequence block per wave.
-hipError_t launch_gemm_blocked(const EnumJob &j, int nw, hipStream_t st);
-// Process-wide choice of nw for the blocked form (runtime.cpp).
+// waves per workgroup (2, 4 or 8), one 256-sequence block per wave; mode 0
+// stages contact tiles through double-buffered LDS, mode 1 through triple-
+// buffered LDS with the next tile's first product overlapping this tile's
+// key updates.
+hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t st);
+// Process-wide launch shape of the blocked form (runtime.cpp).
 int blocked_selected_nw();
+int blocked_selected_mode();
 // Sequences per work item of the persistent batched kernel for a given
 // deepest job (its tile shape is fixed per depth class).
 uint64_t gemm_batch_seqs_per_item(int kb_max);

@@ -127,10 +127,12 @@ const GemmVariant *gemm_selected_variant(int KB)
 }
 
 namespace {
-std::atomic<int> g_blocked_nw{4};   // waves per workgroup of the blocked form
+std::atomic<int> g_blocked_nw{4};     // waves per workgroup of the blocked form
+std::atomic<int> g_blocked_mode{0};   // its staging mode
 }
 
 int blocked_selected_nw() { return g_blocked_nw.load(); }
+int blocked_selected_mode() { return g_blocked_mode.load(); }
 
 }  // namespace hpmap
 
@@ -138,15 +140,24 @@ using namespace hpmap;
 
 extern "C" {
 
-hp_status hp_blocked_select(int nw)
+hp_status hp_blocked_select(int nw, int mode)
 {
     if (nw != 2 && nw != 4 && nw != 8)
         return fail(HP_EINVAL, "blocked form: waves per workgroup must be 2, 4 or 8");
+    if (mode != 0 && mode != 1)
+        return fail(HP_EINVAL, "blocked form: staging mode must be 0 or 1");
     g_blocked_nw.store(nw);
+    g_blocked_mode.store(mode);
     return HP_OK;
 }
 
-int hp_blocked_selected(void) { return g_blocked_nw.load(); }
+void hp_blocked_selected(int *nw, int *mode)
+{
+    if (nw)
+        *nw = g_blocked_nw.load();
+    if (mode)
+        *mode = g_blocked_mode.load();
+}
 
 int hp_gemm_shape_count(uint32_t K_pad)
 {

@@ -113,3 +113,16 @@ def test_blocked_pair_table_weight_three(dims, lo, hi):
     gs = oracle.ground_states(oracle.structures(*dims), lo, hi, table=table)
     _assert_equal({"out": o.cpu().numpy().view(np.uint16), "emin": e.cpu().numpy(),
                    "desig": d.cpu().numpy().view(np.uint64), "nondesign": int(nd.item())}, gs)
+
+
+@pytest.mark.parametrize("nw,mode", [(2, 0), (4, 0), (8, 0), (2, 1), (4, 1), (8, 1)])
+def test_blocked_every_launch_shape(nw, mode):
+    keep = hp.hp_blocked_selected()
+    try:
+        hp.hp_blocked_select(nw, mode)
+        print("blocked shape", nw, mode, flush=True)
+        for dims, lo, hi in [((4, 4, 1), 0, 1 << 16), ((3, 3, 1), 0, 512), ((3, 3, 3), 12345, 14470),
+                             ((6, 6, 1), (1 << 36) - 1500, 1 << 36), ((2, 3, 4), 77, 1077)]:
+            _assert_equal(run(dims, BLK, lo, hi), _oracle(dims, lo, hi))
+    finally:
+        hp.hp_blocked_select(*keep)
