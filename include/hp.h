@@ -185,6 +185,36 @@ hp_status hp_enumerate_symmetric(const hp_structs *s, const void *d_ws, int form
                                  uint64_t *d_designability, uint64_t *d_nondesign, void *stream);
 
 /*
+ * Reversal symmetry in the blocked form (HP_FORM_BLOCKED_I8 geometry; same
+ * requirements).  Blocks are 256 sequences that differ only in the 8 middle
+ * monomers (positions h .. h+7 for even N, h .. h+3 and h+5 .. h+8 around the
+ * middle monomer for odd N, h = (N - 8 - N % 2) / 2); reversal maps blocks
+ * onto blocks.  With a = the h highest monomers, b = the h lowest and b' =
+ * reverse(b), the canonical blocks are those with a <= b'.
+ *   hp_canonical_block_count   number of canonical blocks (0 when the
+ *                        blocked form does not cover the handle): about
+ *                        2^N / 512.
+ *   hp_enumerate_symmetric_blocked  scores canonical blocks [b_lo, b_hi)
+ *                        and fills d_out / d_emin (full 2^N-entry maps,
+ *                        indexed by sequence) at every sequence s of the
+ *                        block and, for blocks with a < b', at reverse(s);
+ *                        designability and the deleterious count add 2 per
+ *                        such s and 1 for the sequences of blocks with
+ *                        a == b' (their reverses lie in the same block).
+ *                        Over [0, hp_canonical_block_count) the outputs equal
+ *                        those of hp_enumerate over [0, 2^N).
+ * Block index order: over the middle monomer (odd N), then row pairs
+ * p < 2^(h-1) of the (a, b') triangle, each holding row b' = p (a = 0 .. p)
+ * followed by row b' = 2^h - 1 - p (a = 0 .. 2^h - 1 - p).
+ * Errors: as hp_enumerate_symmetric; HP_EUNSUPPORTED as HP_FORM_BLOCKED_I8.
+ */
+uint64_t hp_canonical_block_count(const hp_structs *s);
+hp_status hp_enumerate_symmetric_blocked(const hp_structs *s, const void *d_ws, uint64_t b_lo,
+                                         uint64_t b_hi, uint16_t *d_out, int32_t *d_emin,
+                                         uint64_t *d_designability, uint64_t *d_nondesign,
+                                         void *stream);
+
+/*
  * Energy gap and threshold (Methods, end of "HP and MJ lattice models": the
  * threshold is the smallest difference between the lowest and second-lowest
  * fold energies that counts as distinguishable; closer than that, the

@@ -20,10 +20,12 @@ from ._binding import (  # noqa: F401
     hp_autotune,
     hp_blocked_select,
     hp_blocked_selected,
+    hp_canonical_block_count,
     hp_canonical_count,
     hp_enumerate_batch,
     hp_enumerate_gap,
     hp_enumerate_symmetric,
+    hp_enumerate_symmetric_blocked,
     hp_gemm_select,
     hp_gemm_selected,
     hp_gemm_shapes,

@@ -82,6 +82,8 @@ def library():
         "hp_batch_workspace_bytes": (sz, [ctypes.c_int]),
         "hp_canonical_count": (u64, [vp]),
         "hp_enumerate_symmetric": (st, [vp, vp, ctypes.c_int, u64, u64, vp, vp, vp, vp, vp]),
+        "hp_canonical_block_count": (u64, [vp]),
+        "hp_enumerate_symmetric_blocked": (st, [vp, vp, u64, u64, vp, vp, vp, vp, vp]),
         "hp_enumerate_gap": (st, [vp, vp, ctypes.c_int, u64, u64, i32, vp, vp, vp, vp, vp, vp]),
         "hp_sample": (st, [vp, vp, ctypes.c_int, u64, u64, u64, i32, vp, vp, vp, vp, vp, vp, vp]),
         "hp_enumerate_batch": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp, sz, vp]),
@@ -238,6 +240,25 @@ def hp_enumerate(s: Structures, ws, form: int, seq_lo: int, seq_hi: int, out=Non
         _ptr(designability, torch.int64, s.n_class, "designability"),
         _ptr(nondesign, torch.int64, 1, "nondesign"),
         _stream_handle(stream)), "hp_enumerate")
+
+
+def hp_canonical_block_count(s: Structures) -> int:
+    return int(library().hp_canonical_block_count(s.handle))
+
+
+def hp_enumerate_symmetric_blocked(s: Structures, ws, b_lo: int, b_hi: int, out=None, emin=None,
+                                   designability=None, nondesign=None, stream=None):
+    """Canonical blocks [b_lo, b_hi) of the blocked form; out / emin are full
+    2^N maps indexed by sequence (written at s and, off the diagonal, at
+    reverse(s))."""
+    import torch
+    n = 1 << s.N
+    _check(library().hp_enumerate_symmetric_blocked(
+        s.handle, _ptr(ws, torch.uint8, None, "workspace"), b_lo, b_hi,
+        _ptr(out, _U16, n, "out"), _ptr(emin, torch.int32, n, "emin"),
+        _ptr(designability, torch.int64, s.n_class, "designability"),
+        _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)),
+        "hp_enumerate_symmetric_blocked")
 
 
 def hp_enumerate_gap(s: Structures, ws, form: int, seq_lo: int, seq_hi: int, threshold: int = 1,

@@ -89,6 +89,26 @@ hp_status plan_batch(const hp_job *jobs, int njobs, size_t ws_bytes, BatchPlan *
 
 }  // namespace
 
+// Block geometry fields of a job (the blocked form).
+static void set_block_geometry(EnumJob &j, const hp_structs *s, bool canonical)
+{
+    const BlockGeometry g = block_geometry(s->N, canonical);
+    j.blk_vmask = 0;
+    j.blk_pos = 0;
+    for (int x = 0; x < 8; ++x) {
+        j.blk_vmask |= uint64_t(1) << g.pos[x];
+        j.blk_pos |= uint64_t(g.pos[x]) << (8 * x);
+    }
+    j.blk_pp[0] = j.blk_pp[1] = j.blk_pp[2] = 0;
+    for (int n = 0; n < g.npp; ++n)
+        j.blk_pp[n / 8] |= uint64_t(g.pa[n] | (g.pb[n] << 4)) << (8 * (n % 8));
+    j.blk_npp = g.npp;
+    j.half_bits = canonical ? g.half : s->N / 2;
+    j.blk_s2 = j.gemm_b ? reinterpret_cast<const int8_t *>(j.gemm_b) +
+                              (s->ws.blk_s2 - s->ws.gemm_b) + (canonical ? 8 * 64 * 16 : 0)
+                        : nullptr;
+}
+
 EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64_t hi, uint16_t *out,
                  int32_t *emin, uint64_t *desig, uint64_t *nondesign)
 {
@@ -124,8 +144,8 @@ EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
     j.uw = int32_t(s->uw);
     j.MW = int32_t(s->MW);
     j.mode = kSeqPlain;
-    j.half_bits = s->N / 2;
     j.threshold = 1;
+    set_block_geometry(j, s, false);
     return j;
 }
 
@@ -247,6 +267,7 @@ hp_status hp_upload(const hp_structs *s, void *d_ws, size_t ws_bytes, void *stre
         {s->ws.masks, s->masks.data(), s->masks.size() * 4},
         {s->ws.gemm_a, s->gemm_a.data(), s->gemm_a.size()},
         {s->ws.gemm_b, s->gemm_b.data(), s->gemm_b.size()},
+        {s->ws.blk_s2, s->blk_s2.data(), s->blk_s2.size()},
     };
     for (const Part &p : parts) {
         if (!p.bytes)
@@ -390,6 +411,47 @@ hp_status hp_enumerate_symmetric(const hp_structs *s, const void *d_ws, int form
     o.mode = kSeqCanonical;
     return run_blocks(s, d_ws, form, t_lo, t_hi, d_out, d_emin, d_designability, d_nondesign, o,
                       stream, "hp_enumerate_symmetric launch");
+}
+
+uint64_t hp_canonical_block_count(const hp_structs *s)
+{
+    if (!s || !s->blk_ok)
+        return 0;
+    const int odd = s->N & 1;
+    const int h = (s->N - kBlkBits - odd) / 2;
+    const uint64_t tri = h ? (uint64_t(1) << (h - 1)) * ((uint64_t(1) << h) + 1) : 1;
+    return tri * (odd ? 2 : 1);
+}
+
+hp_status hp_enumerate_symmetric_blocked(const hp_structs *s, const void *d_ws, uint64_t b_lo,
+                                         uint64_t b_hi, uint16_t *d_out, int32_t *d_emin,
+                                         uint64_t *d_designability, uint64_t *d_nondesign,
+                                         void *stream)
+{
+    if (!s)
+        return fail(HP_EINVAL, "structures handle is NULL");
+    if (!d_ws)
+        return fail(HP_EINVAL, "workspace pointer is NULL");
+    if (!s->blk_ok)
+        return fail(HP_EUNSUPPORTED, "the blocked form needs pure pair energies, N >= 8 "
+                                     "and A * nbp <= 128");
+    if (b_lo >= b_hi)
+        return fail(HP_EINVAL, "empty block range (b_lo >= b_hi)");
+    if (b_hi > hp_canonical_block_count(s))
+        return fail(HP_EINVAL, "b_hi exceeds the number of canonical blocks");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    constexpr uint64_t kChunk = kBlockSeqs >> kBlkBits;   // canonical blocks per launch
+    for (uint64_t lo = b_lo; lo < b_hi;) {
+        const uint64_t hi = b_hi - lo > kChunk ? lo + kChunk : b_hi;
+        EnumJob j = make_enum_job(s, d_ws, lo, hi, d_out, d_emin, d_designability, d_nondesign);
+        j.mode = kSeqCanonical;
+        set_block_geometry(j, s, true);
+        hipError_t e = launch_gemm_blocked(j, blocked_selected_nw(), blocked_selected_mode(), hs);
+        if (e != hipSuccess)
+            return device_fail(e, "hp_enumerate_symmetric_blocked launch");
+        lo = hi;
+    }
+    return HP_OK;
 }
 
 size_t hp_batch_workspace_bytes(int njobs)

@@ -1,28 +1,32 @@
 // Block-factorised int8-MFMA form of the ground-state search (pure pair
-// energies, plain sequence ranges).
+// energies).
 //
-// A block is 2^8 consecutive sequences: they share every monomer above the
-// low 8 bits.  Splitting each pair (i, j) by whether i and j are low (< 8)
-// or high, the quantity maximised, F = A sum_k C_k(c) h_i h_j (the negated
-// energy of Eq. 1 up to a constant), becomes
-//   F(s, c) = base(c) + sum_{v < 8} h_v w_v(c) + sum_{low pairs} A C_vv'(c) h_v h_v'
-// with base(c) = A sum over high-high contacts of h_i h_j and
-// w_v(c) = A sum over contacts (v, j), j high, of h_j: numbers that depend on
-// the block and the conformation but not on the low bits.  Two products:
+// A block is 256 sequences that differ only in 8 "varying" monomers: the low
+// 8 for plain ranges (256 consecutive sequences), the middle 8 for the
+// reversal-canonical blocks (reversal then maps blocks onto blocks).
+// Splitting each pair (i, j) by whether i and j vary, the quantity
+// maximised, F = A sum_k C_k(c) h_i h_j (the negated energy of Eq. 1 up to a
+// constant), becomes
+//   F(s, c) = base(c) + sum_{v varying} h_v w_v(c) + sum_{varying pairs} A C_vv'(c) h_v h_v'
+// with base(c) = A sum over contacts of two outer monomers of h_i h_j and
+// w_v(c) = A sum over contacts of v with an outer monomer j of h_j: numbers
+// that depend on the block and the conformation but not on the varying
+// monomers.  Two products:
 //
 //   stage one  D1 = V x C1, per 32-conformation tile: V holds 32 block-
-//              dependent "virtual rows" (weights -m2 A on high-high pairs for
-//              base, -m2 A h_j on the pairs of v for w_v, unit rows picking
-//              the 9 low-low pairs and the 2 window index rows) and C1 is the
-//              0/1 contact matrix with the index rows.  D1[m][c] is, for each
-//              conformation, the int8 byte of quantity m: -m2 base, -m2 w_v,
-//              -m2 A C_vv', u & 127 and -(u >> 7).
+//              dependent "virtual rows" (weights -m2 A on outer-outer pairs
+//              for base, -m2 A h_j on the pairs of v for w_v, unit rows
+//              picking the varying pairs and the 2 window index rows) and C1
+//              is the 0/1 contact matrix with the index rows.  D1[m][c] is,
+//              for each conformation, the int8 byte of quantity m: -m2 base,
+//              -m2 w_v, -m2 A C_vv', u & 127 and -(u >> 7).
 //   stage two  key = A2 x S2: A2 = D1 packed to bytes (a lane of the stage-one
 //              result holds one conformation and 16 of its virtual rows,
 //              exactly the 16 bytes it supplies as the A operand of the next
 //              product, so no data moves between lanes), S2 = per-sequence
 //              indicators -128 (1, h_v, h_v h_v') and (1, -128) for the index
-//              bytes.  The accumulator is the window key 128 m2 F + u.
+//              bytes, precomputed on the host per block geometry.  The
+//              accumulator is the window key 128 m2 F + u.
 //
 // Per 32 x 32 (conformation x sequence) tile this issues one MFMA of depth
 // 32 instead of K_pad/32 of them; stage one adds K_pad/32 MFMAs per
@@ -36,57 +40,95 @@ namespace {
 
 constexpr int kBlkTiles = (1 << kBlkBits) / 32;   // sequence tiles per block (8)
 
-// Virtual rows: m = 0 base; 1 .. 8 w_v with v = m - 1; 9 .. 17 the low-low
-// pairs below; 18 and 19 the index bytes; 20 .. 31 zero.
-constexpr int kRowW = 1, kRowVV = 9, kRowIdx = 18;
+// The 8 varying monomers of a block sit at positions pos(x) (x = 0 .. 7,
+// packed 8 bits each in j.blk_pos); j.blk_vmask has their bits.  Virtual
+// rows: m = 0 base; 1 .. 8 w_v for v = pos(m - 1); then one row per pair of
+// varying monomers with odd separation >= 3 (j.blk_npp pairs, x-indices a | b << 4
+// packed a byte each in j.blk_pp[]); then the two index bytes; zero beyond.
+// Plain ranges (CANON false) use the low 8 monomers, a geometry known at
+// compile time: pos(x) = x and the pairs kLow8Pairs, the same list the host
+// lays the second product's operand out by.
+constexpr int kRowW = 1, kRowVV = 9;
 
-// Low-low pairs (a, b) of odd separation >= 3 inside the low 8 monomers.
-// Pairs 0 .. 4: (p, p + 3); 5 .. 7: (p - 5, p); 8: (0, 7).
-__device__ __forceinline__ int vv_a(int p) { return p < 5 ? p : (p < 8 ? p - 5 : 0); }
-__device__ __forceinline__ int vv_b(int p) { return p < 5 ? p + 3 : (p < 8 ? p : 7); }
+template <bool CANON>
+__device__ __forceinline__ int blk_pos(const EnumJob &j, int x)
+{
+    return CANON ? int((j.blk_pos >> (8 * x)) & 0xffu) : x;
+}
 
-// Row of the stage-one result held in accumulator register r of a lane in
-// half `half` of the wave (32 x 32 MFMA result layout).
-__device__ __forceinline__ int d1_row(int r, int half) { return 8 * (r >> 2) + 4 * half + (r & 3); }
+template <bool CANON>
+__device__ __forceinline__ int blk_pair(const EnumJob &j, int p)
+{
+    if (!CANON)
+        return p < 8 ? int((kLow8Pairs >> (8 * p)) & 0xffu) : kLow8Pair8;
+    const uint64_t w = p < 8 ? j.blk_pp[0] : (p < 16 ? j.blk_pp[1] : j.blk_pp[2]);
+    return int((w >> (8 * (p & 7))) & 0xffu);
+}
+
+template <bool CANON>
+__device__ __forceinline__ int blk_npp(const EnumJob &j) { return CANON ? j.blk_npp : kLow8NumPairs; }
+
+template <bool CANON>
+__device__ __forceinline__ uint64_t blk_vmask(const EnumJob &j) { return CANON ? j.blk_vmask : 0xffull; }
 
 // Stage-one A operand: this lane's virtual row m = lane & 31 over product
-// rows k = 32 kb + 16 half + q of C1.
-template <int KB>
+// rows k = 32 kb + 16 half + q of C1, for the block whose outer monomers are
+// the bits of `outer`.
+template <int KB, bool CANON>
 __device__ __forceinline__ void blk_v_fragments(const EnumJob &j, uint64_t outer, int m, int half,
                                                 v4i (&vf)[KB])
 {
-    const uchar4 *rows = reinterpret_cast<const uchar4 *>(j.pairs);
+    const int N = j.N;
     const int coef = j.blk_coef;
-    const int va = m >= kRowVV && m < kRowIdx ? vv_a(m - kRowVV) : -1;
-    const int vb = m >= kRowVV && m < kRowIdx ? vv_b(m - kRowVV) : -1;
+    const uint64_t vmask = blk_vmask<CANON>(j);
+    const int row_idx = kRowVV + blk_npp<CANON>(j);
+    const int wv = m >= kRowW && m < kRowVV ? blk_pos<CANON>(j, m - kRowW) : -1;
+    int va = -1, vb = -1;
+    if (m >= kRowVV && m < row_idx) {
+        const int pr = blk_pair<CANON>(j, m - kRowVV);
+        va = blk_pos<CANON>(j, pr & 15);
+        vb = blk_pos<CANON>(j, pr >> 4);
+    }
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
+        // product row k < K is the pair (i, i + d) of the k-th odd separation
+        // d >= 3 in (d, i) order: find the first row's pair by skipping whole
+        // runs of length N - d, then advance row by row
+        const int kbase = kb * 32 + half * 16;
+        int d = 3, i = kbase;
+        while (d < N && i >= N - d) {
+            i -= N - d;
+            d += 2;
+        }
         uint32_t w[4];
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
             uint32_t word = 0;
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
-                const int k = kb * 32 + half * 16 + q4 * 4 + bb;
+                const int k = kbase + q4 * 4 + bb;
                 int v = 0;
                 if (k == j.K) {
-                    v = m == kRowIdx ? 1 : 0;
+                    v = m == row_idx ? 1 : 0;
                 } else if (k == j.K + 1) {
-                    v = m == kRowIdx + 1 ? -1 : 0;
-                } else if (k < j.K) {
-                    const uchar4 r = rows[k];
-                    const int i = r.x, jj = r.y;
-                    const bool hi_i = i >= kBlkBits, hi_j = jj >= kBlkBits;
-                    const int hh = int((outer >> i) & (outer >> jj) & 1u);
-                    const int hj = int((outer >> jj) & 1u);
+                    v = m == row_idx + 1 ? -1 : 0;
+                } else if (d < N) {
+                    const int jj = i + d;
+                    const bool out_i = !((vmask >> i) & 1u), out_j = !((vmask >> jj) & 1u);
+                    const bool h_i = (outer >> i) & 1u, h_j = (outer >> jj) & 1u;
                     if (m == 0)
-                        v = hi_i && hi_j && hh ? -coef : 0;
+                        v = out_i && out_j && h_i && h_j ? -coef : 0;
                     else if (m < kRowVV)
-                        v = i == m - kRowW && hi_j && hj ? -coef : 0;
-                    else if (m < kRowIdx)
+                        v = (i == wv && out_j && h_j) || (jj == wv && out_i && h_i) ? -coef : 0;
+                    else if (m < row_idx)
                         v = i == va && jj == vb ? -coef : 0;
                 }
                 word |= (uint32_t(v) & 0xffu) << (8 * bb);
+                ++i;   // next row: next i, or the next run
+                if (d < N && i + d >= N) {
+                    i = 0;
+                    d += 2;
+                }
             }
             w[q4] = word;
         }
@@ -94,38 +136,43 @@ __device__ __forceinline__ void blk_v_fragments(const EnumJob &j, uint64_t outer
     }
 }
 
-// Stage-two B operand for sequence tile t of the block: this lane's sequence
-// x = 32 t + (lane & 31) (the low 8 bits), byte q of half `half` carrying the
-// indicator of virtual row d1_row(q, half).
-__device__ __forceinline__ void blk_s_fragments(int col, int half, v4i (&sf)[kBlkTiles])
+// Sequence of block sequence x: the outer bits plus x's bits deposited at the
+// varying positions.
+__device__ __forceinline__ uint64_t blk_sequence(const EnumJob &j, uint64_t outer, int x)
 {
+    uint64_t s = outer;
 #pragma unroll
-    for (int t = 0; t < kBlkTiles; ++t) {
-        const int x = 32 * t + col;
-        uint32_t w[4];
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-            uint32_t word = 0;
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) {
-                const int m = d1_row(q4 * 4 + bb, half);
-                uint32_t byte = 0;
-                if (m == 0)
-                    byte = 0x80u;
-                else if (m < kRowVV)
-                    byte = ((x >> (m - kRowW)) & 1) ? 0x80u : 0u;
-                else if (m < kRowIdx)
-                    byte = ((x >> vv_a(m - kRowVV)) & (x >> vv_b(m - kRowVV)) & 1) ? 0x80u : 0u;
-                else if (m == kRowIdx)
-                    byte = 0x01u;
-                else if (m == kRowIdx + 1)
-                    byte = 0x80u;
-                word |= byte << (8 * bb);
-            }
-            w[q4] = word;
-        }
-        sf[t] = v4i{int(w[0]), int(w[1]), int(w[2]), int(w[3])};
-    }
+    for (int b = 0; b < 8; ++b)
+        s |= uint64_t((x >> b) & 1) << blk_pos<true>(j, b);
+    return s;
+}
+
+// Canonical block index t -> outer bits.  With h = j.half_bits outer bits on
+// each side (low: b, high: a) and, for odd N, the middle monomer m as an
+// outer bit, reversal maps the block (a, m, b) onto (rev b, m, rev a); the
+// canonical blocks are a <= b' = rev(b).  The index runs over m, then row
+// pairs p < 2^(h-1) of the (a, b') triangle, each holding row b' = p
+// (a = 0 .. p) and row b' = 2^h - 1 - p (a = 0 .. 2^h - 1 - p).  *diag is
+// set when a == b', i.e. the block is its own reverse.
+// (Block counts stay below 2^28 for N <= 36, so 32-bit arithmetic suffices.)
+__device__ __forceinline__ uint64_t blk_canonical_outer(const EnumJob &j, uint64_t t64, bool *diag)
+{
+    const int h = j.half_bits;
+    const int odd = j.N & 1;
+    const uint32_t t = uint32_t(t64);
+    const uint32_t side = 1u << h;
+    const uint32_t span = side + 1;
+    const uint32_t per_m = h ? (side >> 1) * span : 1;
+    const uint32_t m = t / per_m;
+    const uint32_t r = t - m * per_m;
+    const uint32_t p = h ? r / span : 0;
+    const uint32_t o = r - p * span;
+    const bool first = o <= p;
+    const uint32_t bp = first ? p : side - 1 - p;
+    const uint32_t a = first ? o : o - p - 1;
+    *diag = a == bp;
+    const uint32_t b = h ? (__builtin_bitreverse32(bp) >> (32 - h)) : 0;
+    return (uint64_t(a) << (h + 8 + odd)) | (uint64_t(m) << (h + 4)) | b;
 }
 
 // Low bytes of four int32 values (each in [-128, 127]) packed little-endian,
@@ -188,7 +235,7 @@ enum { kBlkLds = 0, kBlkPipe = 1 };
 // One wave scores one block of 256 sequences against every conformation
 // tile; the NW waves of a workgroup take consecutive blocks and share the
 // C1 tiles through LDS.
-template <int KB, int NW, int MODE>
+template <int KB, int NW, int MODE, bool CANON>
 __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
 {
     __shared__ v4i lds[(MODE == kBlkPipe ? 3 : 2) * KB * 64];
@@ -196,14 +243,21 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
     const int wave = threadIdx.x >> 6;
     const int col = lane & 31;
     const int half = lane >> 5;
-    const uint64_t blk = (j.lo >> kBlkBits) + uint64_t(blockIdx.x) * NW + wave;
-    const uint64_t outer = blk << kBlkBits;
+    // plain jobs: block = sequences sharing the bits above the low 8, range in
+    // sequences; canonical jobs: range in canonical block indices
+    const uint64_t blk = (CANON ? j.lo : j.lo >> kBlkBits) + uint64_t(blockIdx.x) * NW + wave;
+    bool diag = false;
+    const uint64_t outer = CANON ? blk_canonical_outer(j, blk, &diag) : blk << kBlkBits;
     const v4i *__restrict__ B1 = reinterpret_cast<const v4i *>(j.gemm_b);
 
     v4i vf[KB];
-    blk_v_fragments<KB>(j, outer, col, half, vf);
+    blk_v_fragments<KB, CANON>(j, outer, col, half, vf);
+    // stage-two B operand: per-sequence indicators, precomputed per geometry
     v4i sf[kBlkTiles];
-    blk_s_fragments(col, half, sf);
+    const v4i *__restrict__ S2 = reinterpret_cast<const v4i *>(j.blk_s2);
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t)
+        sf[t] = S2[t * 64 + lane];
 
     int b[kBlkTiles], sc[kBlkTiles], gb[kBlkTiles], gs[kBlkTiles];
 #pragma unroll
@@ -280,19 +334,31 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
         const int ob = __shfl_xor(gb[t], 32);
         const int os = __shfl_xor(gs[t], 32);
         top2_merge(gb[t], gs[t], ob, os);
-        const uint64_t idx = outer + uint64_t(t * 32 + col);
-        finish_sequence(j, idx, idx, idx, half == 0 && idx >= j.lo && idx < j.hi, gb[t], gs[t],
-                        lane == 0, 1);
+        if constexpr (CANON) {
+            // off the diagonal the block's reverse is never scored: write both;
+            // a diagonal block holds each sequence and its reverse itself
+            const uint64_t sq = blk_sequence(j, outer, t * 32 + col);
+            const uint64_t rs = diag ? sq : __builtin_bitreverse64(sq) >> (64 - j.N);
+            finish_sequence(j, sq, sq, rs, half == 0 && blk < j.hi, gb[t], gs[t], lane == 0, 1);
+        } else {
+            const uint64_t idx = outer + uint64_t(t * 32 + col);
+            finish_sequence(j, idx, idx, idx, half == 0 && idx >= j.lo && idx < j.hi, gb[t],
+                            gs[t], lane == 0, 1);
+        }
     }
 }
 
 template <int KB, int NW, int MODE>
 hipError_t launch_blk_shape(const EnumJob &j, hipStream_t st)
 {
-    const uint64_t first = j.lo >> kBlkBits, last = (j.hi - 1) >> kBlkBits;
-    const uint64_t n_blocks = last - first + 1;
+    const bool canon = j.mode == kSeqCanonical;
+    const uint64_t n_blocks =
+        canon ? j.hi - j.lo : ((j.hi - 1) >> kBlkBits) - (j.lo >> kBlkBits) + 1;
     const dim3 grid(unsigned((n_blocks + NW - 1) / NW));
-    hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE>), grid, dim3(NW * 64), 0, st, j);
+    if (canon)
+        hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE, true>), grid, dim3(NW * 64), 0, st, j);
+    else
+        hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE, false>), grid, dim3(NW * 64), 0, st, j);
     return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ struct WsLayout {
     size_t masks = 0;    // uint32_t[n_conf][MW]: W pair words, then unary bit planes
     size_t gemm_a = 0;   // int8_t[n_tiles][K_pad/32][64 lanes][16]
     size_t gemm_b = 0;   // blocked form: int8_t[n_tiles][K_pad/32][64 lanes][16], or none
+    size_t blk_s2 = 0;   // blocked form: int8_t[2 geometries][8 tiles][64 lanes][16], or none
     size_t total = 0;
 };
 
@@ -65,11 +66,31 @@ struct hp_structs {
     std::vector<uint32_t> masks;      // n_conf * W contact bitmasks
     std::vector<int8_t> gemm_a;       // int8 contact matrix in MFMA A-operand order
     std::vector<int8_t> gemm_b;       // blocked form: 0/1 contact matrix + window index rows
+    std::vector<int8_t> blk_s2;       // blocked form: per-sequence operand of the second product
     std::vector<uint8_t> pair_rows;   // K_pad * 4: (i, j, constant, 0) per product row
     hpmap::WsLayout ws;
 };
 
 namespace hpmap {
+
+// Block geometry of the blocked form: the 8 varying monomers pos[0..7]
+// (ascending) -- the low 8 for plain ranges, the middle 8 (around the middle
+// monomer for odd N) for reversal-canonical blocks -- and the pairs among
+// them with odd separation >= 3 as x-indices (a, b), a < b (at most 16).
+// Pairs of the low 8 monomers with odd separation >= 3, as x-indices
+// a | b << 4 a byte each (pairs 0 .. 7) plus the ninth pair: the plain
+// geometry, shared by the host tables and the kernel's compile-time copy.
+constexpr uint64_t kLow8Pairs = 0x6372526141705030ull;   // (0,3) (0,5) (0,7) (1,4) (1,6) (2,5) (2,7) (3,6)
+constexpr int kLow8Pair8 = 0x74;                          // (4,7)
+constexpr int kLow8NumPairs = 9;
+
+struct BlockGeometry {
+    int pos[8];
+    int npp;
+    int pa[16], pb[16];
+    int half;   // canonical blocks: outer monomers on each side
+};
+BlockGeometry block_geometry(int N, bool canonical);
 
 // Host enumeration (structures.cpp).  Returns HP_OK or an error with msg set.
 hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_structs *s,

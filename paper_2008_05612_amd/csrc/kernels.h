@@ -33,6 +33,12 @@ struct EnumJob {
     uint64_t *seqs;                 // sampled mode: the sequence drawn at each index, or null
     uint64_t seed;                  // sampled mode: generator seed
     int32_t blk_shift, blk_win_tiles, blk_coef;   // blocked form: key scale, windows, m2 A
+    // blocked form block geometry: varying monomers (mask; positions packed a
+    // byte each), their odd-separation pairs (x-indices a | b << 4, a byte
+    // each) and how many
+    uint64_t blk_vmask, blk_pos, blk_pp[3];
+    int32_t blk_npp;
+    const int8_t *blk_s2;           // second-product operand of this geometry (8 x 64 x 16 B)
 };
 
 // Index -> sequence maps of a job.  kSeqPlain: index t is sequence t.

@@ -209,6 +209,35 @@ void canonicalise(const Box &b, const uint8_t *walk, uint8_t *out)
 
 }  // namespace
 
+BlockGeometry block_geometry(int N, bool canonical)
+{
+    BlockGeometry g{};
+    const int odd = N & 1;
+    g.half = canonical ? (N - kBlkBits - odd) / 2 : 0;
+    for (int x = 0; x < 8; ++x)
+        g.pos[x] = canonical ? g.half + x + (x >= 4 ? odd : 0) : x;
+    g.npp = 0;
+    if (!canonical) {
+        for (int p = 0; p < kLow8NumPairs; ++p) {
+            const int pr = p < 8 ? int((kLow8Pairs >> (8 * p)) & 0xffu) : kLow8Pair8;
+            g.pa[p] = pr & 15;
+            g.pb[p] = pr >> 4;
+        }
+        g.npp = kLow8NumPairs;
+        return g;
+    }
+    for (int a = 0; a < 8; ++a)
+        for (int b = a + 1; b < 8; ++b) {
+            const int d = g.pos[b] - g.pos[a];
+            if (d >= 3 && d % 2 == 1) {
+                g.pa[g.npp] = a;
+                g.pb[g.npp] = b;
+                ++g.npp;
+            }
+        }
+    return g;
+}
+
 hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_structs *s,
                            std::string *msg)
 {
@@ -523,6 +552,42 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
         }
     }
 
+    // Per-sequence operand of the second product, for both block geometries:
+    // 8 sequence tiles x 64 lanes x 16 bytes in MFMA operand order.  Lane l
+    // holds block sequence x = 32 t + (l & 31); its byte q carries the
+    // indicator of the virtual row m = 8 (q / 4) + 4 (l / 32) + q % 4 (the
+    // row the first product's result register q holds in that lane):
+    // m = 0 the block term (-128), 1 .. 8 the weight of varying monomer m-1
+    // (-128 h), then one row per varying pair (-128 h_a h_b), then the two
+    // index bytes (1 and -128).
+    s->blk_s2.clear();
+    if (s->blk_ok) {
+        s->blk_s2.assign(2 * 8 * 64 * 16, 0);
+        for (int g = 0; g < 2; ++g) {
+            const BlockGeometry geo = block_geometry(N, g == 1);
+            const int row_idx = 9 + geo.npp;
+            for (int t = 0; t < 8; ++t)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int x = 32 * t + (lane & 31), half = lane >> 5;
+                    for (int q = 0; q < 16; ++q) {
+                        const int m = 8 * (q / 4) + 4 * half + q % 4;
+                        int v = 0;
+                        if (m == 0)
+                            v = -128;
+                        else if (m < 9)
+                            v = ((x >> (m - 1)) & 1) ? -128 : 0;
+                        else if (m < row_idx)
+                            v = ((x >> geo.pa[m - 9]) & (x >> geo.pb[m - 9]) & 1) ? -128 : 0;
+                        else if (m == row_idx)
+                            v = 1;
+                        else if (m == row_idx + 1)
+                            v = -128;
+                        s->blk_s2[((size_t(g) * 8 + t) * 64 + lane) * 16 + q] = static_cast<int8_t>(v);
+                    }
+                }
+        }
+    }
+
     // pair table for the popcount form, 4 bytes per row (i, j, 0, 0)
     s->pair_rows.assign(size_t(s->K_pad) * 4, 0);
     for (uint32_t k = 0; k < s->K_pad; ++k) {
@@ -539,7 +604,8 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
     L.masks = up(L.pairs + s->pair_rows.size());
     L.gemm_a = up(L.masks + s->masks.size() * 4);
     L.gemm_b = up(L.gemm_a + s->gemm_a.size());
-    L.total = up(L.gemm_b + s->gemm_b.size());
+    L.blk_s2 = up(L.gemm_b + s->gemm_b.size());
+    L.total = up(L.blk_s2 + s->blk_s2.size());
     return HP_OK;
 }
 

@@ -191,3 +191,39 @@ def test_energy_table_structures(lib):
     big = (ctypes.c_int32 * 4)(0, -100, -100, -300)       # weights beyond int8
     assert lib.hp_structures_energy(3, 3, 3, big, ctypes.byref(h)) == -5
     assert lib.hp_structures_energy(3, 3, 1, None, ctypes.byref(h)) == -1
+
+
+def test_canonical_block_count(lib):
+    # reversal maps blocks (a, m, b) -> (rev b, m, rev a); count the blocks with
+    # a <= rev(b) by brute force and check they cover 2^N sequences once
+    for dims in [(2, 2, 2), (3, 3, 1), (3, 4, 1), (2, 2, 3), (4, 4, 1), (3, 5, 1), (2, 3, 3)]:
+        s = hp.Structures(*dims)
+        N = s.N
+        odd = N & 1
+        h = (N - 8 - odd) // 2
+        rev = lambda x: int(format(x, "0%db" % h)[::-1], 2) if h else 0  # noqa: E731
+        canon = diag = 0
+        for m in range(2 if odd else 1):
+            for a in range(1 << h):
+                for b in range(1 << h):
+                    if a <= rev(b):
+                        canon += 1
+                        diag += a == rev(b)
+        assert hp.hp_canonical_block_count(s) == canon, dims
+        assert 256 * (2 * (canon - diag) + diag) == 1 << N
+    assert hp.hp_canonical_block_count(hp.Structures(3, 3, 3)) == 262656
+    assert hp.hp_canonical_block_count(hp.Structures(2, 3, 1)) == 0
+    assert hp.hp_canonical_block_count(hp.Structures(3, 3, 3, table=(0, -10, -10, -23))) == 0
+
+
+def test_low8_pair_list_is_every_odd_pair():
+    # the plain block geometry's pair list (shared by host tables and kernel)
+    # holds exactly the pairs of the low 8 monomers with odd separation >= 3
+    src = open(os.path.join(ROOT, "paper_2008_05612_amd", "csrc", "hp_internal.h")).read()
+    c = int(re.search(r"kLow8Pairs = (0x[0-9a-f]+)ull", src).group(1), 16)
+    last = int(re.search(r"kLow8Pair8 = (0x[0-9a-f]+);", src).group(1), 16)
+    n = int(re.search(r"kLow8NumPairs = (\d+);", src).group(1))
+    got = [((c >> (8 * p)) & 15, ((c >> (8 * p)) >> 4) & 15) for p in range(8)]
+    got.append((last & 15, last >> 4))
+    want = [(a, b) for a in range(8) for b in range(a + 1, 8) if (b - a) >= 3 and (b - a) % 2]
+    assert n == 9 and sorted(got) == want and len(set(got)) == 9

@@ -126,3 +126,113 @@ def test_blocked_every_launch_shape(nw, mode):
             _assert_equal(run(dims, BLK, lo, hi), _oracle(dims, lo, hi))
     finally:
         hp.hp_blocked_select(*keep)
+
+
+# ---------------------------------------------------------------------------
+# reversal-canonical blocks (hp_enumerate_symmetric_blocked)
+# ---------------------------------------------------------------------------
+
+def _rev(s, N):
+    return int(format(s, "0%db" % N)[::-1], 2)
+
+
+def canonical_block_sequences(N, t):
+    """Sequences of canonical block t as the header documents the order
+    (test-side restatement): returns (list of sequences, diagonal flag)."""
+    odd = N & 1
+    h = (N - 8 - odd) // 2
+    side = 1 << h
+    span = side + 1
+    per_m = (side >> 1) * span if h else 1
+    m, r = divmod(t, per_m)
+    p = r // span if h else 0
+    o = r - p * span
+    first = o <= p
+    bp = p if first else side - 1 - p
+    a = o if first else o - p - 1
+    b = _rev(bp, h) if h else 0
+    pos = [h + x + (odd if x >= 4 else 0) for x in range(8)]
+    outer = (a << (h + 8 + odd)) | (m << (h + 4)) | b
+    seqs = [outer | sum(((x >> k) & 1) << pos[k] for k in range(8)) for x in range(256)]
+    return seqs, a == bp
+
+
+def _sym_run(dims, b_lo, b_hi, out=None, emin=None):
+    import torch
+    s = hp.Structures(*dims)
+    ws = s.workspace()
+    n = 1 << s.N
+    if out is None:
+        out = torch.full((n,), -7, dtype=torch.int16, device="cuda")
+        emin = torch.full((n,), 99, dtype=torch.int32, device="cuda")
+    d = torch.zeros(s.n_class, dtype=torch.int64, device="cuda")
+    nd = torch.zeros(1, dtype=torch.int64, device="cuda")
+    print("symmetric blocked", dims, b_lo, b_hi, flush=True)
+    hp.hp_enumerate_symmetric_blocked(s, ws, b_lo, b_hi, out, emin, d, nd)
+    torch.cuda.synchronize()
+    return s, out, emin, d, nd
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (3, 3, 1), (3, 4, 1), (2, 2, 3), (4, 4, 1), (3, 5, 1),
+                                  (2, 3, 3)])
+def test_symmetric_blocked_full_small_maps(dims):
+    s = hp.Structures(*dims)
+    nb = hp.hp_canonical_block_count(s)
+    s, out, emin, d, nd = _sym_run(dims, 0, nb)
+    N = s.N
+    _assert_equal({"out": out.cpu().numpy().view(np.uint16), "emin": emin.cpu().numpy(),
+                   "desig": d.cpu().numpy().view(np.uint64), "nondesign": int(nd.item())},
+                  _oracle(dims, 0, 1 << N))
+
+
+def test_symmetric_blocked_full_3x3x3_equals_plain():
+    import torch
+    s = hp.Structures(3, 3, 3)
+    nb = hp.hp_canonical_block_count(s)
+    assert nb == 262656
+    third = nb // 3 + 17
+    s, out, emin, d, nd = _sym_run((3, 3, 3), 0, third)
+    d2 = torch.zeros_like(d)
+    nd2 = torch.zeros_like(nd)
+    hp.hp_enumerate_symmetric_blocked(s, s.workspace(), third, nb, out, emin, d2, nd2)
+    o1, d1, n1 = _full_map_invariants((3, 3, 3), BLK)
+    assert torch.equal(out, o1)
+    assert np.array_equal((d + d2).cpu().numpy().view(np.uint64), d1)
+    assert int(nd.item()) + int(nd2.item()) == n1
+
+
+@pytest.mark.parametrize("dims", [(6, 6, 1), (3, 3, 3), (5, 5, 1)])
+def test_symmetric_blocked_windows_match_oracle(dims):
+    import torch
+    s = hp.Structures(*dims)
+    N = s.N
+    nb = hp.hp_canonical_block_count(s)
+    st = oracle.structures(*dims)
+    rng = np.random.default_rng(0x5EB + N)
+    big = N > 30     # 6x6: the uint16 map alone is 137 GB; no energies, no full scan
+    out = torch.empty((1 << N,), dtype=torch.int16, device="cuda")
+    emin = None if big else torch.empty((1 << N,), dtype=torch.int32, device="cuda")
+    for b0 in [0, nb - 3] + [int(x) for x in rng.integers(0, nb - 3, 2)]:
+        out.fill_(-7)
+        if emin is not None:
+            emin.fill_(99)
+        _sym_run(dims, b0, b0 + 3, out, emin)
+        seqs, revs = [], []
+        for t in range(b0, b0 + 3):
+            sq, diag = canonical_block_sequences(N, t)
+            seqs += sq
+            if not diag:
+                revs += [_rev(x, N) for x in sq]
+        ref = oracle.ground_states_gap(st, seqs)
+        idx = torch.tensor(seqs, dtype=torch.int64, device="cuda")
+        assert np.array_equal(out[idx].cpu().numpy().view(np.uint16), ref.out)
+        if emin is not None:
+            assert np.array_equal(emin[idx].cpu().numpy(), ref.emin)
+        if revs:
+            ridx = torch.tensor(revs, dtype=torch.int64, device="cuda")
+            rref = oracle.ground_states_gap(st, revs)
+            assert np.array_equal(out[ridx].cpu().numpy().view(np.uint16), rref.out)
+        # nothing outside the scored blocks and their reverses was written
+        if not big:
+            touched = int((out != -7).sum().item())
+            assert touched == len(set(seqs) | set(revs))
