@@ -1,20 +1,23 @@
 """Full genotype-phenotype map of one lattice, streamed in sequence blocks.
 
-    python -m paper_2008_05612_amd.fullmap --lattice 6x6 [--form gemm|popcount]
+    python -m paper_2008_05612_amd.fullmap --lattice 6x6 [--form blocked|gemm|popcount]
         [--symmetric] [--block-bits 30] [--neighbors] [--checkpoint FILE] [--json OUT]
 
-Every block of 2^block_bits sequences is one hp_enumerate launch; a progress
-line is printed per block.  With --symmetric only the canonical sequences
-s <= reverse(s) are scored (hp_enumerate_symmetric, about half the work),
-each result is written at both s and reverse(s), and the blocks run over
-canonical indices.  The uint16 map stays resident on the device
-(2^36 x 2 B = 137 GB for 6x6) unless --no-map is given.  With --checkpoint,
-the accumulated designability is written after every block and a rerun
-resumes after the last finished block (the map of skipped blocks is then not
-available, so --neighbors is refused on a resumed run).
+Every step of 2^block_bits sequences is one library call; a progress line is
+printed per step.  The default form is the block-factorised int8 form where
+it applies (pure pair energies), else the dense int8 form.  With --symmetric
+only reversal-canonical work is scored (about half): canonical sequences
+s <= reverse(s) for the dense and popcount forms (hp_enumerate_symmetric),
+canonical blocks for the blocked form (hp_enumerate_symmetric_blocked); each
+result is written at both s and reverse(s), and the steps run over canonical
+indices.  The uint16 map stays resident on the device (2^36 x 2 B = 137 GB
+for 6x6) unless --no-map is given.  With --checkpoint, the accumulated
+designability is written after every step and a rerun resumes after the last
+finished step (the map of skipped steps is then not available, so
+--neighbors is refused on a resumed run).
 
 All device work goes through the C ABI (hp_enumerate, hp_enumerate_symmetric,
-hp_neighbors).
+hp_enumerate_symmetric_blocked, hp_neighbors).
 """
 from __future__ import annotations
 
@@ -55,7 +58,7 @@ def _save_checkpoint(path, dims, form, block_bits, symmetric, next_block, desig,
     os.replace(tmp, path)
 
 
-def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=False,
+def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
         checkpoint=None, progress=print, device="cuda", symmetric=False, table=None):
     """Enumerate all 2^N sequences of the box; returns a summary dict (and the
     device map under key "map" when keep_map)."""
@@ -66,8 +69,18 @@ def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=Fals
     ws = s.workspace(device)
     N = s.N
     total = 1 << N
-    space = hp.hp_canonical_count(s) if symmetric else total   # indices to process
-    block = 1 << min(block_bits, N)
+    if form is None:
+        form = hp.FORM_BLOCKED_I8 if hp.hp_canonical_block_count(s) else hp.FORM_GEMM_I8
+    blocked_sym = symmetric and form == hp.FORM_BLOCKED_I8
+    # indices to process: sequences, canonical sequences, or canonical blocks
+    # of 256 sequences; one step covers 2^block_bits sequences' worth
+    if blocked_sym:
+        space = hp.hp_canonical_block_count(s)
+        block = 1 << max(0, min(block_bits, N) - 8)
+    else:
+        space = hp.hp_canonical_count(s) if symmetric else total
+        block = 1 << min(block_bits, N)
+    per_index = 256 if blocked_sym else 1
     n_blocks = (space + block - 1) // block
     desig = torch.zeros(s.n_class, dtype=torch.int64, device=device)
     nond = torch.zeros(1, dtype=torch.int64, device=device)
@@ -85,7 +98,9 @@ def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=Fals
     for b in range(start_block, n_blocks):
         lo, hi = b * block, min((b + 1) * block, space)
         tb = time.time()
-        if symmetric:
+        if blocked_sym:
+            hp.hp_enumerate_symmetric_blocked(s, ws, lo, hi, out, None, desig, nond)
+        elif symmetric:
             hp.hp_enumerate_symmetric(s, ws, form, lo, hi, out, None, desig, nond)
         else:
             hp.hp_enumerate(s, ws, form, lo, hi, out[lo:hi] if out is not None else None, None,
@@ -101,12 +116,13 @@ def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=Fals
     summary = {
         "lattice": "x".join(str(x) for x in dims if x > 1) or "1",
         "N": N, "sequences": total, "n_conf": s.n_conf, "n_class": s.n_class,
-        "form": "gemm_i8" if form == hp.FORM_GEMM_I8 else "popcount",
-        "symmetric": symmetric, "scored_sequences": space,
-        "blocks": n_blocks, "block_sequences": block, "resumed_at_block": start_block,
+        "form": {hp.FORM_GEMM_I8: "gemm_i8", hp.FORM_BLOCKED_I8: "blocked_i8"}.get(form, "popcount"),
+        "symmetric": symmetric, "scored_sequences": space * per_index,
+        "blocks": n_blocks, "block_sequences": block * per_index, "resumed_at_block": start_block,
         "wall_s": wall,
-        "evals_per_s": (space - start_block * block) * s.n_conf / wall,
-        "map_evals_per_s": (space - start_block * block) * s.n_conf / wall * (total / space),
+        "evals_per_s": (space - start_block * block) * per_index * s.n_conf / wall,
+        "map_evals_per_s": ((space - start_block * block) * per_index * s.n_conf / wall *
+                            (total / (space * per_index))),
         "designing": int(d.sum()), "nondesign": nd,
         "designable_classes": int((d > 0).sum()),
         "top_class": int(d.argmax()), "top_designability": int(d.max()),
@@ -143,7 +159,7 @@ def run(dims, form=hp.FORM_GEMM_I8, block_bits=30, keep_map=True, neighbors=Fals
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--lattice", default="6x6")
-    ap.add_argument("--form", choices=["gemm", "popcount"], default="gemm")
+    ap.add_argument("--form", choices=["blocked", "gemm", "popcount"], default=None)
     ap.add_argument("--block-bits", type=int, default=30)
     ap.add_argument("--symmetric", action="store_true")
     ap.add_argument("--neighbors", action="store_true")
@@ -151,7 +167,8 @@ def main(argv=None):
     ap.add_argument("--checkpoint")
     ap.add_argument("--json")
     a = ap.parse_args(argv)
-    form = hp.FORM_GEMM_I8 if a.form == "gemm" else hp.FORM_POPCOUNT
+    form = {None: None, "blocked": hp.FORM_BLOCKED_I8, "gemm": hp.FORM_GEMM_I8,
+            "popcount": hp.FORM_POPCOUNT}[a.form]
     res = run(_parse_lattice(a.lattice), form, a.block_bits, keep_map=not a.no_map,
               neighbors=a.neighbors, checkpoint=a.checkpoint,
               progress=lambda m: print(m, flush=True), symmetric=a.symmetric)

@@ -1,7 +1,8 @@
 """Full-map driver: checkpoint/resume, and the full 6x6 map.
 
-The 6x6 map (2^36 sequences x 57337 conformations, 137 GB resident) takes
-about 11 minutes, so it only runs when HP_RUN_FULLMAP=1.  Its parity checks:
+The 6x6 map (2^36 sequences x 57337 conformations, 137 GB resident; the
+blocked form over reversal-canonical blocks) takes a few minutes, so it only
+runs when HP_RUN_FULLMAP=1.  Its parity checks:
 the sum and symmetry invariants over all 2^36 sequences (symmetry on a large
 random sample), oracle windows at both ends and at seeded offsets, and the
 popcount form on sampled windows.
@@ -53,7 +54,8 @@ def test_checkpoint_resume_is_identical(tmp_path):
     assert np.array_equal(ref["_designability"], gs.designability)
 
 
-def test_checkpoint_resume_symmetric(tmp_path):
+@pytest.mark.parametrize("form", [None, hp.FORM_GEMM_I8, hp.FORM_POPCOUNT])
+def test_checkpoint_resume_symmetric(tmp_path, form):
     dims = (4, 4, 1)
     ref = fullmap.run(dims, block_bits=10, keep_map=False, progress=lambda m: None)
     ck = str(tmp_path / "cks.json")
@@ -65,17 +67,19 @@ def test_checkpoint_resume_symmetric(tmp_path):
             raise _Stop()
 
     with pytest.raises(_Stop):
-        fullmap.run(dims, block_bits=10, keep_map=False, checkpoint=ck, symmetric=True,
-                    progress=stop_after_two)
-    res = fullmap.run(dims, block_bits=10, keep_map=False, checkpoint=ck, symmetric=True,
-                      progress=lambda m: None)
+        fullmap.run(dims, form=form, block_bits=10, keep_map=False, checkpoint=ck,
+                    symmetric=True, progress=stop_after_two)
+    res = fullmap.run(dims, form=form, block_bits=10, keep_map=False, checkpoint=ck,
+                      symmetric=True, progress=lambda m: None)
     assert res["resumed_at_block"] == 2 and res["scored_sequences"] < 1 << 16
+    assert res["form"] == {None: "blocked_i8", hp.FORM_GEMM_I8: "gemm_i8",
+                           hp.FORM_POPCOUNT: "popcount"}[form]
     assert np.array_equal(res["_designability"], ref["_designability"])
     assert res["nondesign"] == ref["nondesign"]
 
 
 @pytest.mark.skipif(os.environ.get("HP_RUN_FULLMAP") != "1",
-                    reason="full 6x6 map takes ~6 min; set HP_RUN_FULLMAP=1")
+                    reason="full 6x6 map takes minutes; set HP_RUN_FULLMAP=1")
 def test_full_6x6_map():
     import torch
     res = fullmap.run((6, 6, 1), neighbors=True, symmetric=True,
