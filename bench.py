@@ -34,6 +34,9 @@ METRIC = ("seq×structure evals/s + full-map wall time (3×3×3, 6×6); "
 PEAK_INT8_TOPS = 5000.0          # MI355X dense int8 MFMA, TOP/s
 PEAK_VALU_TOPS = 256 * 2.4e9 * 64 / 1e12   # 32-bit VALU lane-ops/s: 256 CU x 64 lanes/clk x 2.4 GHz
 EPILOGUE_OPS_PER_PAIR = 1.25     # v_med3 + v_max3 per two keys, one v_max3 per four
+# with two VALU instructions issued per quad-cycle (gfx950 dual issue; the
+# popcount form's two-operand instructions reach it, the key updates do not)
+PEAK_VALU_DUAL_TOPS = 2 * PEAK_VALU_TOPS
 
 
 def parse():
@@ -266,6 +269,18 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
     res["dense_gemm_i8_mfma_issued_frac"] = (2.0 * s.K_pad * total * s.n_conf /
                                              (t.ms() * 1e-3) / 1e12 / PEAK_INT8_TOPS)
     res["blocked_map_equals_dense_map"] = bool(torch.equal(dense, blocked_map))
+    # the same full map from reversal-canonical blocks only (about half the work)
+    nb = hp.hp_canonical_block_count(s)
+    dsym = torch.zeros(s.n_class, dtype=torch.int64, device=dev)
+    hp.hp_enumerate_symmetric_blocked(s, ws, 0, 1024, dense, None, dsym)
+    torch.cuda.synchronize()
+    dsym.zero_()
+    t.start()
+    hp.hp_enumerate_symmetric_blocked(s, ws, 0, nb, dense, None, dsym)
+    t.stop()
+    torch.cuda.synchronize()
+    res["symmetric_blocked_full_map_ms_3x3x3"] = t.ms()
+    res["symmetric_blocked_map_equals_blocked_map"] = bool(torch.equal(dense, blocked_map))
     del dense
     n = 1 << 24
     for form, name in ((hp.FORM_POPCOUNT, "popcount"), (hp.FORM_BLOCKED_I8, "blocked_i8")):
@@ -281,9 +296,9 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
     res["dense_over_popcount_3x3x3"] = (res["dense_gemm_i8_evals_per_s"] /
                                         res["3x3x3_slice_popcount_evals_per_s"])
     # the popcount loop issues 2W + 4 VALU instructions per pair (W ANDs, W
-    # bit counts, 4 for the key and top-2 update)
+    # bit counts, 4 for the key and top-2 update); its mix dual-issues
     res["popcount_valu_frac_3x3x3"] = (res["3x3x3_slice_popcount_evals_per_s"] *
-                                       (2 * s.W + 4) / (PEAK_VALU_TOPS * 1e12))
+                                       (2 * s.W + 4) / (PEAK_VALU_DUAL_TOPS * 1e12))
     # sampling mode (device-side draws): one launch of 2^14 draws -- the
     # launch size of the paper's sampling runs -- and one of 2^24; the
     # per-sequence time is the unit of the paper's CPU/GPU comparison table
@@ -309,6 +324,14 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
     res["6x6_sample_2^22_s_per_sequence"] = t.ms() * 1e-3 / (1 << 22)
     n6 = 1 << 28
     d6 = torch.zeros(s6.n_class, dtype=torch.int64, device=dev)
+    nb6 = hp.hp_canonical_block_count(s6)
+    hp.hp_enumerate_symmetric_blocked(s6, ws6, 0, 1024, None, None, d6)
+    torch.cuda.synchronize()
+    t.start()
+    hp.hp_enumerate_symmetric_blocked(s6, ws6, 0, 1 << 20, None, None, d6)
+    t.stop()
+    torch.cuda.synchronize()
+    res["6x6_full_map_s_extrapolated_symmetric_blocked"] = t.ms() * 1e-3 * nb6 / (1 << 20)
     for form, name, nn in ((hp.FORM_BLOCKED_I8, "blocked_i8", n6), (hp.FORM_GEMM_I8, "gemm_i8", n6),
                            (hp.FORM_POPCOUNT, "popcount", n6 // 4)):
         hp.hp_enumerate(s6, ws6, form, 0, 1 << 16, None, None, d6)
@@ -333,11 +356,11 @@ def cpu_baseline(dims, seconds):
     import oracle
     st = oracle.structures(*dims)
     lo = 0
-    n = 256
+    n = 4096          # enough to keep every host thread busy while calibrating
     t0 = time.perf_counter()
     oracle.ground_states(st, lo, lo + n)
     dt = time.perf_counter() - t0
-    n = int(max(256, min(1 << 20, n * seconds / max(dt, 1e-3))))
+    n = int(max(4096, min(1 << 22, n * seconds / max(dt, 1e-3))))
     t0 = time.perf_counter()
     oracle.ground_states(st, lo, lo + n)
     dt = time.perf_counter() - t0
