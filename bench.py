@@ -52,8 +52,9 @@ def parse():
                          "use the fastest for its extra measurement")
     ap.add_argument("--nw", type=int, default=4,
                     help="waves per workgroup of the blocked form (2, 4 or 8)")
-    ap.add_argument("--blk-mode", type=int, default=0,
-                    help="staging mode of the blocked form (0 double-buffered, 1 pipelined)")
+    ap.add_argument("--blk-mode", type=int, default=-1,
+                    help="staging mode of the blocked form (0 double-buffered, 1 pipelined, "
+                         "2 second operand in LDS, -1 by product depth)")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: no extras, no CPU baseline, plus a 256 MiB device "
                          "copy used to calibrate the HBM byte counters")
@@ -106,7 +107,8 @@ def main():
     if args.autotune:
         _, tune_ms = hp.hp_autotune(s, ws, 0, 1 << 20, repeats=2)
     hp.hp_blocked_select(args.nw, args.blk_mode)
-    kname = "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, args.nw, args.blk_mode)
+    blk_mode = args.blk_mode if args.blk_mode >= 0 else (2 if s.K_pad <= 192 else 0)
+    kname = "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, args.nw, blk_mode)
     pairs = total * n_conf
 
     out = torch.empty(total, dtype=torch.int16, device=dev)
@@ -183,7 +185,7 @@ def main():
                         "counts + union-find",
             "lattice": "3x3x3", "N": N, "sequences": total, "n_conf": n_conf,
             "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "form": "blocked_i8",
-            "waves_per_workgroup": args.nw, "staging_mode": args.blk_mode,
+            "waves_per_workgroup": args.nw, "staging_mode": blk_mode,
         },
         "roofline": {
             "bound": "alu",
@@ -364,9 +366,19 @@ def cpu_baseline(dims, seconds):
     t0 = time.perf_counter()
     oracle.ground_states(st, lo, lo + n)
     dt = time.perf_counter() - t0
-    return {"value": n * st.n_conf / dt, "unit": "evals/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # one thread on a smaller sample of the same window
+    oracle.set_num_threads(1)
+    n1 = max(64, n // (4 * cores))
+    t0 = time.perf_counter()
+    oracle.ground_states(st, lo, lo + n1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
+    return {"value": n * st.n_conf / dt, "unit": "evals/s", "cores": cores,
             "kind": "oracle",
-            "sample": "3x3x3, sequences [0, %d) x all %d conformations, %.1f s" % (n, st.n_conf, dt)}
+            "sample": "3x3x3, sequences [0, %d) x all %d conformations, %.1f s" % (n, st.n_conf, dt),
+            "value_1_thread": n1 * st.n_conf / dt1,
+            "sample_1_thread": "sequences [0, %d), %.1f s" % (n1, dt1)}
 
 
 if __name__ == "__main__":

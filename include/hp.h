@@ -296,9 +296,11 @@ void hp_graph_free(hp_graph *g);
  * Launch shape of HP_FORM_BLOCKED_I8: every wave scores one block of 256
  * sequences.  hp_blocked_select sets, process-wide, the waves per workgroup
  * nw (2, 4 or 8; default 4; the waves of a workgroup share each staged
- * contact tile) and the staging mode (0, default: double-buffered LDS; 1:
+ * contact tile) and the staging mode (0: double-buffered LDS; 1:
  * triple-buffered LDS with the block-level product of the next tile issued
- * while the current tile's keys are updated).  hp_blocked_selected reports
+ * while the current tile's keys are updated; 2: as 0, with the per-sequence
+ * operand of the second product read from LDS instead of held in registers;
+ * -1, default: 2 for K_pad <= 192, else 0).  hp_blocked_selected reports
  * them (either pointer may be NULL).  Results never depend on the shape.
  * Errors: HP_EINVAL for another value.
  */

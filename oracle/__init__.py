@@ -73,6 +73,7 @@ def lib():
             "or_neighbors": (None, [c_int, u16p, c_long, u64p, u64p, u64p, c_int, u64p]),
             "or_components": (None, [c_int, u16p, u32p]),
             "or_num_threads": (c_int, []),
+            "or_set_num_threads": (None, [c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -89,6 +90,11 @@ def _p(a: np.ndarray, ct):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results never change)."""
+    lib().or_set_num_threads(int(n))
 
 
 def count_walks(X: int, Y: int, Z: int = 1) -> int:

@@ -772,3 +772,16 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads later parallel loops use (no effect
+ * without OpenMP); results do not depend on it. */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

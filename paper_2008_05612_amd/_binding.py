@@ -290,9 +290,10 @@ def hp_sample(s: Structures, ws, form: int, seed: int, idx_lo: int, idx_hi: int,
         _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)), "hp_sample")
 
 
-def hp_blocked_select(nw: int, mode: int = 0):
+def hp_blocked_select(nw: int, mode: int = -1):
     """Launch shape of the blocked int8 form: waves per workgroup (2, 4 or 8)
-    and staging mode (0 double-buffered, 1 pipelined)."""
+    and staging mode (0 double-buffered, 1 pipelined, 2 operand in LDS, -1 by
+    product depth)."""
     _check(library().hp_blocked_select(nw, mode), "hp_blocked_select")
 
 

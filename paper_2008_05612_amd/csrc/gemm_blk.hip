@@ -224,13 +224,34 @@ __device__ __forceinline__ void stage_two(const v4i &a2, const v4i (&sf)[kBlkTil
     }
 }
 
+// Stage two with the per-sequence operand read from LDS just before each
+// product (32 fewer live registers than keeping it in VGPRs).
+__device__ __forceinline__ void stage_two_lds(const v4i &a2, const v4i *s2, int lane,
+                                              int (&b)[kBlkTiles], int (&sc)[kBlkTiles])
+{
+    const v16i zero = {};
+    v16i acc[2];
+    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, s2[lane], zero, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t) {
+        if (t + 1 < kBlkTiles)
+            acc[(t + 1) & 1] =
+                __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, s2[(t + 1) * 64 + lane], zero, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; r += 2)
+            top2_add2(b[t], sc[t], acc[t & 1][r], acc[t & 1][r + 1]);
+    }
+}
+
 // Staging of the C1 tiles:
 //   kBlkLds  : double-buffered LDS, one barrier per tile; stage one of a tile
 //              runs right before its stage two.
 //   kBlkPipe : triple-buffered LDS; the stage-one products of tile t+1 are
 //              issued during iteration t, so the matrix pipe works on them
 //              while the vector ALU runs tile t's key updates.
-enum { kBlkLds = 0, kBlkPipe = 1 };
+//   kBlkLdsS2: as kBlkLds, with the per-sequence operand of stage two held in
+//              LDS (shared by the workgroup) instead of registers.
+enum { kBlkLds = 0, kBlkPipe = 1, kBlkLdsS2 = 2 };
 
 // One wave scores one block of 256 sequences against every conformation
 // tile; the NW waves of a workgroup take consecutive blocks and share the
@@ -239,6 +260,7 @@ template <int KB, int NW, int MODE, bool CANON>
 __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
 {
     __shared__ v4i lds[(MODE == kBlkPipe ? 3 : 2) * KB * 64];
+    __shared__ v4i s2lds[MODE == kBlkLdsS2 ? kBlkTiles * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 31;
@@ -253,11 +275,16 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
     v4i vf[KB];
     blk_v_fragments<KB, CANON>(j, outer, col, half, vf);
     // stage-two B operand: per-sequence indicators, precomputed per geometry
-    v4i sf[kBlkTiles];
+    v4i sf[MODE == kBlkLdsS2 ? 1 : kBlkTiles];
     const v4i *__restrict__ S2 = reinterpret_cast<const v4i *>(j.blk_s2);
+    if constexpr (MODE == kBlkLdsS2) {
+        for (int i = threadIdx.x; i < kBlkTiles * 64; i += NW * 64)
+            s2lds[i] = S2[i];   // made visible by the barrier before the tile loop
+    } else {
 #pragma unroll
-    for (int t = 0; t < kBlkTiles; ++t)
-        sf[t] = S2[t * 64 + lane];
+        for (int t = 0; t < kBlkTiles; ++t)
+            sf[t] = S2[t * 64 + lane];
+    }
 
     int b[kBlkTiles], sc[kBlkTiles], gb[kBlkTiles], gs[kBlkTiles];
 #pragma unroll
@@ -272,7 +299,7 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
 
     TileStage<KB, NW> stg;
     constexpr int TV = KB * 64;   // vectors per staged tile
-    if constexpr (MODE == kBlkLds) {
+    if constexpr (MODE == kBlkLds || MODE == kBlkLdsS2) {
         stg.load(B1, 0);
         stg.store(lds);
         __syncthreads();
@@ -281,7 +308,10 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
             if (more)
                 stg.load(B1, tile + 1);
             const v16i d1 = stage_one<KB>(vf, lds + (tile & 1) * TV, lane);
-            stage_two(pack_d1(d1), sf, b, sc);
+            if constexpr (MODE == kBlkLdsS2)
+                stage_two_lds(pack_d1(d1), s2lds, lane, b, sc);
+            else
+                stage_two(pack_d1(d1), sf, b, sc);
             if (tile + 1 == wend) {
                 fold_window<kBlkTiles>(b, sc, gb, gs, conf_base, win_shift);
                 conf_base += win_tiles * kTileConf;
@@ -365,6 +395,13 @@ hipError_t launch_blk_shape(const EnumJob &j, hipStream_t st)
 template <int KB>
 hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
 {
+    if (mode == kBlkLdsS2) {
+        switch (nw) {
+        case 2: return launch_blk_shape<KB, 2, kBlkLdsS2>(j, st);
+        case 8: return launch_blk_shape<KB, 8, kBlkLdsS2>(j, st);
+        default: return launch_blk_shape<KB, 4, kBlkLdsS2>(j, st);
+        }
+    }
     if (mode == kBlkPipe) {
         switch (nw) {
         case 2: return launch_blk_shape<KB, 2, kBlkPipe>(j, st);
@@ -383,6 +420,11 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
 
 hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t st)
 {
+    // automatic staging: shallow products keep the second operand in LDS,
+    // which frees registers for a fourth wave per SIMD (measured faster for
+    // K_pad <= 160, slower for 320)
+    if (mode < 0)
+        mode = j.KB <= 6 ? kBlkLdsS2 : kBlkLds;
     switch (j.KB) {
     case 1: return launch_blk<1>(j, nw, mode, st);
     case 2: return launch_blk<2>(j, nw, mode, st);

@@ -128,7 +128,7 @@ const GemmVariant *gemm_selected_variant(int KB)
 
 namespace {
 std::atomic<int> g_blocked_nw{4};     // waves per workgroup of the blocked form
-std::atomic<int> g_blocked_mode{0};   // its staging mode
+std::atomic<int> g_blocked_mode{-1};  // its staging mode; -1: by product depth
 }
 
 int blocked_selected_nw() { return g_blocked_nw.load(); }
@@ -144,8 +144,8 @@ hp_status hp_blocked_select(int nw, int mode)
 {
     if (nw != 2 && nw != 4 && nw != 8)
         return fail(HP_EINVAL, "blocked form: waves per workgroup must be 2, 4 or 8");
-    if (mode != 0 && mode != 1)
-        return fail(HP_EINVAL, "blocked form: staging mode must be 0 or 1");
+    if (mode < -1 || mode > 2)
+        return fail(HP_EINVAL, "blocked form: staging mode must be -1, 0, 1 or 2");
     g_blocked_nw.store(nw);
     g_blocked_mode.store(mode);
     return HP_OK;

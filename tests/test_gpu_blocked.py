@@ -115,7 +115,8 @@ def test_blocked_pair_table_weight_three(dims, lo, hi):
                    "desig": d.cpu().numpy().view(np.uint64), "nondesign": int(nd.item())}, gs)
 
 
-@pytest.mark.parametrize("nw,mode", [(2, 0), (4, 0), (8, 0), (2, 1), (4, 1), (8, 1)])
+@pytest.mark.parametrize("nw,mode", [(2, 0), (4, 0), (8, 0), (2, 1), (4, 1), (8, 1), (2, 2), (4, 2),
+                                     (8, 2)])
 def test_blocked_every_launch_shape(nw, mode):
     keep = hp.hp_blocked_selected()
     try:
