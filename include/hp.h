@@ -256,14 +256,19 @@ hp_status hp_sample(const hp_structs *s, const void *d_ws, int form, uint64_t se
 
 /*
  * Batched launch: several enumeration jobs, possibly of different lattices
- * and uneven sizes, processed by ONE persistent kernel launch that takes
- * fixed-size sequence tiles from a shared work list.  Each job has the
- * meaning of one hp_enumerate call.  d_batch_ws is caller device memory of
- * hp_batch_workspace_bytes(njobs) bytes holding the work list and its
- * counter (both rewritten by every call).  The descriptor upload is a
- * synchronous host-to-device copy made before the launch is enqueued.
+ * and uneven sizes, from one work list of fixed-size items (256 sequences
+ * for HP_FORM_GEMM_I8, 4 blocks of 256 for HP_FORM_BLOCKED_I8).  Jobs are
+ * grouped by product depth (hp_info.K_pad) and each group is one kernel
+ * launch, compiled for that depth, with one workgroup per item; the groups
+ * are enqueued back to back on `stream`.  HP_FORM_POPCOUNT runs the jobs as
+ * separate hp_enumerate calls.  Each job has the meaning of one hp_enumerate
+ * call.  d_batch_ws is caller device memory of hp_batch_workspace_bytes(njobs)
+ * bytes holding the work list (rewritten by every call).  The descriptor
+ * upload is a synchronous host-to-device copy made before the launches are
+ * enqueued.
  * Errors: as hp_enumerate, for any job; HP_EINVAL if njobs < 1 or the
- * workspace is too small.
+ * workspace is too small; HP_EUNSUPPORTED if a job's handle is not covered
+ * by HP_FORM_BLOCKED_I8.
  */
 typedef struct {
     const hp_structs *structs;
@@ -281,10 +286,11 @@ hp_status hp_enumerate_batch(const hp_job *jobs, int njobs, int form, void *d_ba
 
 /*
  * Captured launches: hp_graph_capture_batch records the device work of
- * hp_enumerate_batch (counter reset and persistent kernel, no memsets) into
- * a hipGraph once; hp_graph_launch replays it on `stream`.  The work list is
- * uploaded at capture time and must stay in d_batch_ws while the graph is
- * used.  Designability counters accumulate on every replay.
+ * hp_enumerate_batch (the per-depth kernel launches; no memsets) into a
+ * hipGraph once, for HP_FORM_GEMM_I8 or HP_FORM_BLOCKED_I8; hp_graph_launch
+ * replays it on `stream`.  The work list is uploaded at capture time and must
+ * stay in d_batch_ws while the graph is used.  Designability counters
+ * accumulate on every replay.
  */
 typedef struct hp_graph hp_graph;
 hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *d_batch_ws,

@@ -43,48 +43,91 @@ hp_status check_range(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
 
 struct BatchPlan {
     std::vector<char> host;   // header + jobs + item starts
-    int kb_max = 0;
-    int n_items = 0;
+    struct Group {
+        int kb, item_lo, item_hi;   // product depth and its items
+    };
+    std::vector<Group> groups;
 };
 
-hp_status plan_batch(const hp_job *jobs, int njobs, size_t ws_bytes, BatchPlan *plan)
+// Work list of a batch: jobs ordered by product depth (stable), items of
+// gemm_batch_seqs_per_item() sequences (dense form) or of
+// blk_batch_seqs_per_item() sequences in whole 256-sequence blocks (blocked
+// form), and the item range of each depth.
+hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, BatchPlan *plan)
 {
     if (!jobs || njobs < 1)
         return fail(HP_EINVAL, "batch needs at least one job");
     if (ws_bytes < hp_batch_workspace_bytes(njobs))
         return fail(HP_EINVAL, "batch workspace too small");
+    const bool blocked = form == HP_FORM_BLOCKED_I8;
     int kb_max = 1;
     for (int i = 0; i < njobs; ++i) {
         hp_status st = check_range(jobs[i].structs, jobs[i].d_ws, jobs[i].seq_lo, jobs[i].seq_hi);
         if (st != HP_OK)
             return st;
+        if (blocked && !jobs[i].structs->blk_ok)
+            return fail(HP_EUNSUPPORTED, "the blocked form needs pure pair energies, N >= 8 "
+                                         "and A * nbp <= 128");
         kb_max = std::max(kb_max, int(jobs[i].structs->K_pad / 32));
     }
-    const uint64_t per = gemm_batch_seqs_per_item(kb_max);
+    std::vector<int> order(njobs);
+    for (int i = 0; i < njobs; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return jobs[a].structs->K_pad < jobs[b].structs->K_pad;
+    });
     std::vector<int64_t> start(njobs + 1, 0);
-    for (int i = 0; i < njobs; ++i) {
-        const uint64_t n = jobs[i].seq_hi - jobs[i].seq_lo;
-        start[i + 1] = start[i] + int64_t((n + per - 1) / per);
+    for (int r = 0; r < njobs; ++r) {
+        const hp_job &jb = jobs[order[r]];
+        uint64_t items;
+        if (blocked) {
+            const uint64_t nblk = ((jb.seq_hi - 1) >> kBlkBits) - (jb.seq_lo >> kBlkBits) + 1;
+            const uint64_t per = blk_batch_seqs_per_item() >> kBlkBits;
+            items = (nblk + per - 1) / per;
+        } else {
+            const uint64_t per = gemm_batch_seqs_per_item();
+            items = (jb.seq_hi - jb.seq_lo + per - 1) / per;
+        }
+        start[r + 1] = start[r] + int64_t(items);
     }
     if (start[njobs] > INT32_MAX)
         return fail(HP_ERANGE, "batch has too many work items");
     plan->host.assign(hp_batch_workspace_bytes(njobs), 0);
     BatchHeader hdr{};
-    hdr.counter = 0;
+    hdr.reserved = 0;
     hdr.njobs = njobs;
     hdr.n_items = int32_t(start[njobs]);
     hdr.kb_max = kb_max;
     std::memcpy(plan->host.data(), &hdr, sizeof(hdr));
     EnumJob *ej = reinterpret_cast<EnumJob *>(plan->host.data() + sizeof(BatchHeader));
-    for (int i = 0; i < njobs; ++i)
-        ej[i] = make_enum_job(jobs[i].structs, jobs[i].d_ws, jobs[i].seq_lo, jobs[i].seq_hi,
-                         jobs[i].d_out, jobs[i].d_emin, jobs[i].d_designability,
-                         jobs[i].d_nondesign);
+    plan->groups.clear();
+    for (int r = 0; r < njobs; ++r) {
+        const hp_job &jb = jobs[order[r]];
+        ej[r] = make_enum_job(jb.structs, jb.d_ws, jb.seq_lo, jb.seq_hi, jb.d_out, jb.d_emin,
+                              jb.d_designability, jb.d_nondesign);
+        const int kb = int(jb.structs->K_pad / 32);
+        if (plan->groups.empty() || plan->groups.back().kb != kb)
+            plan->groups.push_back({kb, int(start[r]), int(start[r])});
+        plan->groups.back().item_hi = int(start[r + 1]);
+    }
     std::memcpy(plan->host.data() + sizeof(BatchHeader) + sizeof(EnumJob) * njobs, start.data(),
                 sizeof(int64_t) * (njobs + 1));
-    plan->kb_max = kb_max;
-    plan->n_items = hdr.n_items;
     return HP_OK;
+}
+
+// One launch per product depth of the plan, in order on `st`.
+hipError_t launch_plan(const BatchPlan &plan, int form, void *d_batch_ws, hipStream_t st)
+{
+    for (const BatchPlan::Group &g : plan.groups) {
+        if (g.item_hi <= g.item_lo)
+            continue;
+        hipError_t e = form == HP_FORM_BLOCKED_I8
+                           ? launch_gemm_blk_batch(d_batch_ws, g.kb, g.item_lo, g.item_hi, st)
+                           : launch_gemm_batch(d_batch_ws, g.kb, g.item_lo, g.item_hi, st);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -477,19 +520,19 @@ hp_status hp_enumerate_batch(const hp_job *jobs, int njobs, int form, void *d_ba
         }
         return (jobs && njobs >= 1) ? HP_OK : fail(HP_EINVAL, "batch needs at least one job");
     }
-    if (form != HP_FORM_GEMM_I8)
+    if (form != HP_FORM_GEMM_I8 && form != HP_FORM_BLOCKED_I8)
         return fail(HP_EINVAL, "unknown kernel form");
     if (!d_batch_ws)
         return fail(HP_EINVAL, "batch workspace is NULL");
     BatchPlan plan;
-    hp_status st = plan_batch(jobs, njobs, batch_ws_bytes, &plan);
+    hp_status st = plan_batch(jobs, njobs, form, batch_ws_bytes, &plan);
     if (st != HP_OK)
         return st;
     // synchronous upload: the host plan is released on return
     hipError_t e = hipMemcpy(d_batch_ws, plan.host.data(), plan.host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess)
         return device_fail(e, "batch upload");
-    e = launch_gemm_batch(d_batch_ws, plan.kb_max, plan.n_items, hs);
+    e = launch_plan(plan, form, d_batch_ws, hs);
     if (e != hipSuccess)
         return device_fail(e, "batch launch");
     return HP_OK;
@@ -501,12 +544,12 @@ hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *
     if (!out)
         return fail(HP_EINVAL, "out pointer is NULL");
     *out = nullptr;
-    if (form != HP_FORM_GEMM_I8)
-        return fail(HP_EUNSUPPORTED, "graph capture is provided for the int8 form");
+    if (form != HP_FORM_GEMM_I8 && form != HP_FORM_BLOCKED_I8)
+        return fail(HP_EUNSUPPORTED, "graph capture is provided for the int8 forms");
     if (!d_batch_ws)
         return fail(HP_EINVAL, "batch workspace is NULL");
     BatchPlan plan;
-    hp_status st = plan_batch(jobs, njobs, batch_ws_bytes, &plan);
+    hp_status st = plan_batch(jobs, njobs, form, batch_ws_bytes, &plan);
     if (st != HP_OK)
         return st;
     hipError_t e = hipMemcpy(d_batch_ws, plan.host.data(), plan.host.size(), hipMemcpyHostToDevice);
@@ -522,7 +565,7 @@ hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *
     }
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_gemm_batch(d_batch_ws, plan.kb_max, plan.n_items, cap);
+        hipError_t le = launch_plan(plan, form, d_batch_ws, cap);
         e = hipStreamEndCapture(cap, &g->graph);
         if (le != hipSuccess)
             e = le;

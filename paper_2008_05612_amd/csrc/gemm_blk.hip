@@ -256,18 +256,19 @@ enum { kBlkLds = 0, kBlkPipe = 1, kBlkLdsS2 = 2 };
 // One wave scores one block of 256 sequences against every conformation
 // tile; the NW waves of a workgroup take consecutive blocks and share the
 // C1 tiles through LDS.
+// The work of one workgroup: wave w scores block blk0 + w (plain jobs: the
+// 256 sequences sharing the bits above the low 8, block index = sequence >> 8;
+// canonical jobs: canonical block index).  lds holds the staged C1 tiles,
+// s2lds the stage-two operand (mode kBlkLdsS2).  Starts and ends at a
+// workgroup barrier, so consecutive calls may reuse the LDS.
 template <int KB, int NW, int MODE, bool CANON>
-__global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
+__device__ __forceinline__ void blk_body(const EnumJob &j, uint64_t blk0, v4i *lds, v4i *s2lds)
 {
-    __shared__ v4i lds[(MODE == kBlkPipe ? 3 : 2) * KB * 64];
-    __shared__ v4i s2lds[MODE == kBlkLdsS2 ? kBlkTiles * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 31;
     const int half = lane >> 5;
-    // plain jobs: block = sequences sharing the bits above the low 8, range in
-    // sequences; canonical jobs: range in canonical block indices
-    const uint64_t blk = (CANON ? j.lo : j.lo >> kBlkBits) + uint64_t(blockIdx.x) * NW + wave;
+    const uint64_t blk = blk0 + wave;
     bool diag = false;
     const uint64_t outer = CANON ? blk_canonical_outer(j, blk, &diag) : blk << kBlkBits;
     const v4i *__restrict__ B1 = reinterpret_cast<const v4i *>(j.gemm_b);
@@ -378,6 +379,53 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
     }
 }
 
+template <int KB, int NW, int MODE, bool CANON>
+__global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
+{
+    __shared__ v4i lds[(MODE == kBlkPipe ? 3 : 2) * KB * 64];
+    __shared__ v4i s2lds[MODE == kBlkLdsS2 ? kBlkTiles * 64 : 1];
+    const uint64_t blk0 = (CANON ? j.lo : j.lo >> kBlkBits) + uint64_t(blockIdx.x) * NW;
+    blk_body<KB, NW, MODE, CANON>(j, blk0, lds, s2lds);
+}
+
+// Batched form for jobs of one product depth: workgroup b scores item
+// item_lo + b, NW consecutive blocks of the job whose item range holds it.
+template <int KB, int NW, int MODE>
+__global__ __launch_bounds__(NW * 64) void k_gemm_blk_batch(BatchHeader *hdr, int item_lo)
+{
+    __shared__ v4i lds[2 * KB * 64];
+    __shared__ v4i s2lds[MODE == kBlkLdsS2 ? kBlkTiles * 64 : 1];
+    const EnumJob *jobs = reinterpret_cast<const EnumJob *>(hdr + 1);
+    const int njobs = hdr->njobs;
+    const int64_t *start = reinterpret_cast<const int64_t *>(jobs + njobs);
+    {
+        // uniform indices let the job be read with scalar loads instead of
+        // occupying vector registers
+        const int it = item_lo + int(blockIdx.x);
+        int lo = 0, hi = njobs - 1;   // job with start[job] <= it < start[job+1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (start[mid] <= it)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const EnumJob &j = jobs[lo];
+        const uint64_t blk0 = (j.lo >> kBlkBits) + uint64_t(it - start[lo]) * NW;
+        blk_body<KB, NW, MODE, false>(j, blk0, lds, s2lds);
+    }
+}
+
+template <int KB>
+hipError_t launch_blk_batch_kb(BatchHeader *hdr, int item_lo, unsigned grid, hipStream_t st)
+{
+    constexpr int MODE = KB <= 6 ? kBlkLdsS2 : kBlkLds;
+    hipLaunchKernelGGL((k_gemm_blk_batch<KB, 4, MODE>), dim3(grid), dim3(256), 0, st, hdr,
+                       item_lo);
+    return hipGetLastError();
+}
+
 template <int KB, int NW, int MODE>
 hipError_t launch_blk_shape(const EnumJob &j, hipStream_t st)
 {
@@ -417,6 +465,30 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
 }
 
 }  // namespace
+
+uint64_t blk_batch_seqs_per_item() { return uint64_t(4) << kBlkBits; }
+
+hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, int item_lo, int item_hi,
+                                 hipStream_t st)
+{
+    BatchHeader *hdr = static_cast<BatchHeader *>(d_batch_ws);
+    const unsigned grid = unsigned(item_hi - item_lo);
+    switch (kb) {
+    case 1: return launch_blk_batch_kb<1>(hdr, item_lo, grid, st);
+    case 2: return launch_blk_batch_kb<2>(hdr, item_lo, grid, st);
+    case 3: return launch_blk_batch_kb<3>(hdr, item_lo, grid, st);
+    case 4: return launch_blk_batch_kb<4>(hdr, item_lo, grid, st);
+    case 5: return launch_blk_batch_kb<5>(hdr, item_lo, grid, st);
+    case 6: return launch_blk_batch_kb<6>(hdr, item_lo, grid, st);
+    case 7: return launch_blk_batch_kb<7>(hdr, item_lo, grid, st);
+    case 8: return launch_blk_batch_kb<8>(hdr, item_lo, grid, st);
+    case 9: return launch_blk_batch_kb<9>(hdr, item_lo, grid, st);
+    case 10: return launch_blk_batch_kb<10>(hdr, item_lo, grid, st);
+    case 11: return launch_blk_batch_kb<11>(hdr, item_lo, grid, st);
+    case 12: return launch_blk_batch_kb<12>(hdr, item_lo, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t st)
 {

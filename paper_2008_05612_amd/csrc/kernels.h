@@ -47,9 +47,12 @@ struct EnumJob {
 // generator (results are written at t - lo).
 enum SeqMode { kSeqPlain = 0, kSeqCanonical = 1, kSeqSampled = 2 };
 
-// Work list of a batched launch, laid out in the batch workspace.
+// Work list of a batched launch, laid out in the batch workspace: this
+// header, EnumJob[njobs] ordered by product depth, int64 item_start[njobs+1].
+// One launch per product depth covers the items of its jobs, one workgroup
+// per item.
 struct BatchHeader {
-    uint32_t counter;     // next item to take (reset to 0 by a fill kernel)
+    uint32_t reserved;
     int32_t njobs;
     int32_t n_items;
     int32_t kb_max;
@@ -79,15 +82,19 @@ hipError_t launch_popcount(const EnumJob &j, hipStream_t st);
 // buffered LDS with the next tile's first product overlapping this tile's
 // key updates.
 hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t st);
+// Persistent batched launch of the blocked form (plain jobs): items of
+// blk_batch_seqs_per_item() sequences (4 blocks), same work-list layout.
+uint64_t blk_batch_seqs_per_item();
+hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, int item_lo, int item_hi,
+                                 hipStream_t st);
 // Process-wide launch shape of the blocked form (runtime.cpp).
 int blocked_selected_nw();
 int blocked_selected_mode();
-// Sequences per work item of the persistent batched kernel for a given
-// deepest job (its tile shape is fixed per depth class).
-uint64_t gemm_batch_seqs_per_item(int kb_max);
-// Batched persistent launch: header at d_ws, then EnumJob[njobs], then
-// int64 item_start[njobs + 1].
-hipError_t launch_gemm_batch(void *d_batch_ws, int kb_max, int n_items, hipStream_t st);
+// Sequences per work item of the dense persistent batched kernel.
+uint64_t gemm_batch_seqs_per_item();
+// Persistent launch over items [item_lo, item_hi) of the work list at
+// d_batch_ws, all of product depth kb.
+hipError_t launch_gemm_batch(void *d_batch_ws, int kb, int item_lo, int item_hi, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, uint64_t n,
                            hipStream_t st);

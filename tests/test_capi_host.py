@@ -157,6 +157,10 @@ def test_argument_errors(lib):
     assert lib.hp_enumerate_batch(jobs, 1, 1, fake_ws, 1 << 20, None) == -1   # empty job
     g = ctypes.c_void_p()
     assert lib.hp_graph_capture_batch(jobs, 1, 0, fake_ws, 1 << 20, ctypes.byref(g)) == -5
+    tiny = hp.Structures(2, 2, 1)      # N < 8: not covered by the blocked form
+    jobs[0] = _binding._Job(tiny.handle.value, 256, 0, 16, None, None, None, None)
+    assert lib.hp_enumerate_batch(jobs, 1, 2, fake_ws, 1 << 20, None) == -5
+    assert lib.hp_graph_capture_batch(jobs, 1, 2, fake_ws, 1 << 20, ctypes.byref(g)) == -5
 
 
 def test_workspace_layout(lib):

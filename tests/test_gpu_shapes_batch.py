@@ -91,9 +91,15 @@ BATCH = [((4, 4, 1), 0, 1 << 16), ((5, 5, 1), 3, 3 + 50001), ((2, 3, 4), 1 << 20
          ((3, 3, 3), 12345, 12345 + 2048), ((2, 2, 1), 0, 16), ((4, 4, 1), 100, 7000)]
 
 
-def _batch_jobs():
+# the blocked form needs N >= 8: the 2x2 job is left out; ranges cut blocks
+BATCH_BLOCKED = [((4, 4, 1), 0, 1 << 16), ((5, 5, 1), 3, 3 + 50001),
+                 ((2, 3, 4), (1 << 20) + 7, (1 << 20) + 4099), ((3, 3, 3), 12345, 12345 + 2048),
+                 ((4, 4, 1), 100, 7000), ((6, 6, 1), (1 << 35) - 1000, (1 << 35) + 777)]
+
+
+def _batch_jobs(batch=None):
     jobs, bufs = [], []
-    for dims, lo, hi in BATCH:
+    for dims, lo, hi in (BATCH if batch is None else batch):
         s, ws = _get(dims)
         b = _alloc(s, hi - lo)
         bufs.append(b)
@@ -101,15 +107,17 @@ def _batch_jobs():
     return jobs, bufs
 
 
-def test_batch_matches_oracle():
+@pytest.mark.parametrize("form", [hp.FORM_GEMM_I8, hp.FORM_BLOCKED_I8])
+def test_batch_matches_oracle(form):
     import torch
-    jobs, bufs = _batch_jobs()
+    batch = BATCH if form == hp.FORM_GEMM_I8 else BATCH_BLOCKED
+    jobs, bufs = _batch_jobs(batch)
     bws = torch.zeros(hp._binding.batch_workspace_bytes(len(jobs)), dtype=torch.uint8,
                       device="cuda")
-    print("batch of", len(jobs), flush=True)
-    hp.hp_enumerate_batch(jobs, hp.FORM_GEMM_I8, bws)
+    print("batch of", len(jobs), "form", form, flush=True)
+    hp.hp_enumerate_batch(jobs, form, bws)
     torch.cuda.synchronize()
-    for (dims, lo, hi), b in zip(BATCH, bufs):
+    for (dims, lo, hi), b in zip(batch, bufs):
         _check(_host(*b), oracle.ground_states(oracle.structures(*dims), lo, hi))
 
 
@@ -124,13 +132,15 @@ def test_batch_popcount_form_matches_oracle():
         _check(_host(*b), oracle.ground_states(oracle.structures(*dims), lo, hi))
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("form", [hp.FORM_GEMM_I8, hp.FORM_BLOCKED_I8])
+def test_graph_replays_match_eager(form):
     import torch
-    jobs, bufs = _batch_jobs()
+    batch = BATCH if form == hp.FORM_GEMM_I8 else BATCH_BLOCKED
+    jobs, bufs = _batch_jobs(batch)
     bws = torch.zeros(hp._binding.batch_workspace_bytes(len(jobs)), dtype=torch.uint8,
                       device="cuda")
-    g = hp.hp_graph_capture_batch(jobs, hp.FORM_GEMM_I8, bws)
-    refs = [oracle.ground_states(oracle.structures(*dims), lo, hi) for dims, lo, hi in BATCH]
+    g = hp.hp_graph_capture_batch(jobs, form, bws)
+    refs = [oracle.ground_states(oracle.structures(*dims), lo, hi) for dims, lo, hi in batch]
     for replay in range(1, 4):
         for o, e, d, nd in bufs:      # outputs overwritten; counters keep accumulating
             o.fill_(-7)
