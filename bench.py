@@ -48,8 +48,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true",
-                    help="time every compiled tile shape of the dense int8 form first and "
-                         "use the fastest for its extra measurement")
+                    help="time every launch shape of the blocked form and every tile shape of "
+                         "the dense form first, and use the fastest")
     ap.add_argument("--nw", type=int, default=4,
                     help="waves per workgroup of the blocked form (2, 4 or 8)")
     ap.add_argument("--blk-mode", type=int, default=-1,
@@ -105,11 +105,14 @@ def main():
         args.no_extra = True
         args.no_cpu_baseline = True
     tune_ms = None
+    hp.hp_blocked_select(args.nw, args.blk_mode)
+    nw = args.nw
+    blk_mode = args.blk_mode if args.blk_mode >= 0 else (2 if s.K_pad <= 192 else 0)
     if args.autotune:
         _, tune_ms = hp.hp_autotune(s, ws, 0, 1 << 20, repeats=2)
-    hp.hp_blocked_select(args.nw, args.blk_mode)
-    blk_mode = args.blk_mode if args.blk_mode >= 0 else (2 if s.K_pad <= 192 else 0)
-    kname = "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, args.nw, blk_mode)
+        (nw, blk_mode), blk_ms = hp.hp_autotune_blocked(s, ws, 0, 1 << 22, repeats=2)
+        tune_ms = {"dense": tune_ms, "blocked": blk_ms}
+    kname = "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, nw, blk_mode)
     pairs = total * n_conf
 
     out = torch.empty(total, dtype=torch.int16, device=dev)
@@ -186,7 +189,7 @@ def main():
                         "counts + union-find",
             "lattice": "3x3x3", "N": N, "sequences": total, "n_conf": n_conf,
             "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "form": "blocked_i8",
-            "waves_per_workgroup": args.nw, "staging_mode": blk_mode,
+            "waves_per_workgroup": nw, "staging_mode": blk_mode,
         },
         "roofline": {
             "bound": "alu",

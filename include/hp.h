@@ -312,6 +312,19 @@ void hp_graph_free(hp_graph *g);
  */
 hp_status hp_blocked_select(int nw, int mode);
 void hp_blocked_selected(int *nw, int *mode);
+/*
+ * hp_autotune_blocked -- time the 9 launch shapes of HP_FORM_BLOCKED_I8
+ * (nw = 2, 4, 8 x mode = 0, 1, 2; entry i is nw = {2,4,8}[i / 3], mode =
+ * i % 3) on sequences [seq_lo, seq_lo + n_seq) (no outputs written, `repeats`
+ * launches each after one warm-up), select the fastest process-wide, and
+ * report per-shape milliseconds in ms[9] and the choice (any pointer may be
+ * NULL).  Synchronises `stream`.
+ * Errors: HP_EUNSUPPORTED for a handle the blocked form does not cover;
+ * HP_EINVAL for a range outside [0, 2^N); HP_EDEVICE for a failed launch.
+ */
+hp_status hp_autotune_blocked(const hp_structs *s, const void *d_ws, uint64_t seq_lo,
+                              uint64_t n_seq, int repeats, float *ms, int *best_nw,
+                              int *best_mode, void *stream);
 
 /*
  * Tile shapes of the int8 form and their autotuning.  Several shapes are

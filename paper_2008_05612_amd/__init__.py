@@ -18,6 +18,7 @@ from ._binding import (  # noqa: F401
     hp_components,
     hp_enumerate,
     hp_autotune,
+    hp_autotune_blocked,
     hp_blocked_select,
     hp_blocked_selected,
     hp_canonical_block_count,

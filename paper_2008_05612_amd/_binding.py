@@ -94,6 +94,9 @@ def library():
         "hp_neighbors": (st, [vp, vp, vp, vp, vp, i32, vp, vp]),
         "hp_components": (st, [vp, vp, vp, vp, vp, vp, vp]),
         "hp_blocked_select": (st, [ctypes.c_int, ctypes.c_int]),
+        "hp_autotune_blocked": (st, [vp, vp, u64, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     vp]),
         "hp_blocked_selected": (None, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "hp_gemm_shape_count": (ctypes.c_int, [ctypes.c_uint32]),
         "hp_gemm_shape_info": (st, [ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -240,6 +243,19 @@ def hp_enumerate(s: Structures, ws, form: int, seq_lo: int, seq_hi: int, out=Non
         _ptr(designability, torch.int64, s.n_class, "designability"),
         _ptr(nondesign, torch.int64, 1, "nondesign"),
         _stream_handle(stream)), "hp_enumerate")
+
+
+def hp_autotune_blocked(s: Structures, ws, seq_lo: int = 0, n_seq: int = 1 << 20,
+                        repeats: int = 2, stream=None):
+    """Time the 9 blocked-form launch shapes, select the fastest; returns
+    ((nw, mode), [ms per shape in hp.h order])."""
+    import torch
+    ms = (ctypes.c_float * 9)()
+    nw, mode = ctypes.c_int(), ctypes.c_int()
+    _check(library().hp_autotune_blocked(s.handle, _ptr(ws, torch.uint8, None, "workspace"), seq_lo,
+                                         n_seq, repeats, ms, ctypes.byref(nw), ctypes.byref(mode),
+                                         _stream_handle(stream)), "hp_autotune_blocked")
+    return (nw.value, mode.value), list(ms)
 
 
 def hp_canonical_block_count(s: Structures) -> int:

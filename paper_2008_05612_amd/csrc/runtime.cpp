@@ -260,4 +260,62 @@ hp_status hp_autotune(const hp_structs *s, const void *d_ws, uint64_t seq_lo, ui
     return HP_OK;
 }
 
+hp_status hp_autotune_blocked(const hp_structs *s, const void *d_ws, uint64_t seq_lo,
+                              uint64_t n_seq, int repeats, float *ms, int *best_nw,
+                              int *best_mode, void *stream)
+{
+    if (!s || !d_ws)
+        return fail(HP_EINVAL, "NULL structures or workspace");
+    if (!s->blk_ok)
+        return fail(HP_EUNSUPPORTED, "the blocked form does not cover this handle");
+    if (n_seq == 0 || seq_lo + n_seq > (uint64_t(1) << s->N) || seq_lo + n_seq < seq_lo)
+        return fail(HP_EINVAL, "tuning range outside [0, 2^N)");
+    if (repeats < 1)
+        repeats = 1;
+    static const int kNW[3] = {2, 4, 8};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess)
+        err = hipEventCreate(&e1);
+    int bi = -1;
+    float best_t = 0.f;
+    EnumJob j = make_enum_job(s, d_ws, seq_lo, seq_lo + n_seq, nullptr, nullptr, nullptr, nullptr);
+    for (int i = 0; i < 9 && err == hipSuccess; ++i) {
+        const int nw = kNW[i / 3], mode = i % 3;
+        err = launch_gemm_blocked(j, nw, mode, st);   // warm-up
+        if (err == hipSuccess)
+            err = hipEventRecord(e0, st);
+        for (int r = 0; r < repeats && err == hipSuccess; ++r)
+            err = launch_gemm_blocked(j, nw, mode, st);
+        if (err == hipSuccess)
+            err = hipEventRecord(e1, st);
+        if (err == hipSuccess)
+            err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess)
+            err = hipEventElapsedTime(&t, e0, e1);
+        t /= float(repeats);
+        if (ms)
+            ms[i] = t;
+        if (err == hipSuccess && (bi < 0 || t < best_t)) {
+            bi = i;
+            best_t = t;
+        }
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (err != hipSuccess)
+        return fail(HP_EDEVICE, std::string("hp_autotune_blocked: ") + hipGetErrorString(err));
+    g_blocked_nw.store(kNW[bi / 3]);
+    g_blocked_mode.store(bi % 3);
+    if (best_nw)
+        *best_nw = kNW[bi / 3];
+    if (best_mode)
+        *best_mode = bi % 3;
+    return HP_OK;
+}
+
 }  // extern "C"

@@ -145,6 +145,9 @@ def test_argument_errors(lib):
     assert lib.hp_enumerate(t96.handle, fake_ws, 2, 0, 16, None, None, None, None, None) == -5
     assert lib.hp_enumerate(s.handle, fake_ws, 3, 0, 16, None, None, None, None, None) == -1
     assert lib.hp_blocked_select(3, 0) == -1 and lib.hp_blocked_select(4, 3) == -1
+    assert lib.hp_autotune_blocked(tiny.handle, fake_ws, 0, 16, 1, None, None, None, None) == -5
+    assert lib.hp_autotune_blocked(s.handle, fake_ws, 0, (1 << 16) + 1, 1, None, None, None,
+                                   None) == -1
     assert hp.hp_blocked_selected() == (4, -1)
     assert lib.hp_upload(s.handle, fake_ws, 10, None) == -1
     assert lib.hp_upload(s.handle, ctypes.c_void_p(257), 1 << 30, None) == -1

@@ -237,3 +237,16 @@ def test_symmetric_blocked_windows_match_oracle(dims):
         if not big:
             touched = int((out != -7).sum().item())
             assert touched == len(set(seqs) | set(revs))
+
+
+def test_autotune_blocked_selects_a_shape_and_keeps_results():
+    keep = hp.hp_blocked_selected()
+    try:
+        s = hp.Structures(5, 5, 1)
+        (nw, mode), ms = hp.hp_autotune_blocked(s, s.workspace(), 0, 1 << 18, repeats=1)
+        assert (nw, mode) == hp.hp_blocked_selected()
+        assert nw in (2, 4, 8) and mode in (0, 1, 2) and len(ms) == 9 and min(ms) > 0
+        assert ms[[2, 4, 8].index(nw) * 3 + mode] == min(ms)
+        _assert_equal(run((5, 5, 1), BLK, 777, 777 + 5000), _oracle((5, 5, 1), 777, 777 + 5000))
+    finally:
+        hp.hp_blocked_select(*keep)
