@@ -71,6 +71,7 @@ def lib():
             "or_splitmix64": (c_u64, [c_u64, c_u64]),
             "or_sample_sequences": (None, [c_u64, c_u64, c_u64, c_int, u64p]),
             "or_neighbors": (None, [c_int, u16p, c_long, u64p, u64p, u64p, c_int, u64p]),
+            "or_phi_counts": (None, [c_int, u16p, c_long, u64p]),
             "or_components": (None, [c_int, u16p, u32p]),
             "or_num_threads": (c_int, []),
             "or_set_num_threads": (None, [c_int]),
@@ -330,6 +331,18 @@ def neighbors(N: int, phen: np.ndarray, n_class: int, phi_q: int = -1) -> Neighb
                        _p(dele, ctypes.c_uint64), _p(oth, ctypes.c_uint64), phi_q,
                        _p(row, ctypes.c_uint64))
     return Neighbors(neu[:n_class], dele[:n_class], oth[:n_class], row if phi_q >= 0 else None)
+
+
+def phi_counts(N: int, phen: np.ndarray, n_class: int) -> np.ndarray:
+    """Numerators of phi_pq (Eq. 2) for every class pair: a uint64 matrix of
+    n_class rows (phenotype q of the genotype) and n_class + 1 columns
+    (phenotype p of the single-point mutant; column n_class = deleterious).
+    phi_pq = counts[q, p] / (N * N_q)."""
+    m = np.ascontiguousarray(phen, dtype=np.uint16)
+    assert m.shape[0] == 1 << N
+    c = np.zeros((max(n_class, 1), n_class + 1), dtype=np.uint64)
+    lib().or_phi_counts(N, _p(m, ctypes.c_uint16), n_class, _p(c, ctypes.c_uint64))
+    return c[:n_class]
 
 
 def components(N: int, phen: np.ndarray) -> np.ndarray:

@@ -731,6 +731,29 @@ void or_neighbors(int N, const uint16_t *map, long n_class, uint64_t *neutral,
     }
 }
 
+/* The whole matrix behind phi_pq (Eq. 2): phi_pq is the mean, over the N_q
+ * genotypes g of phenotype q, of the fraction of g's N single-point mutants
+ * whose phenotype is p.  counts[q * (n_class + 1) + p] receives the number of
+ * (genotype of q, mutant of phenotype p) pairs, so phi_pq = counts / (N N_q);
+ * column n_class counts deleterious mutants (phi_del).  Genotypes whose id is
+ * not a phenotype (0xFFFF or >= n_class) have no row; such mutant ids go to
+ * the deleterious column.  counts has n_class rows; all entries are += .    */
+void or_phi_counts(int N, const uint16_t *map, long n_class, uint64_t *counts)
+{
+    uint64_t total = (uint64_t)1 << N;
+    for (uint64_t g = 0; g < total; g++) {
+        long q = map[g];
+        if (q >= n_class)
+            continue;
+        for (int i = 0; i < N; i++) {
+            long p = map[g ^ ((uint64_t)1 << i)];
+            if (p >= n_class)
+                p = n_class;
+            counts[(uint64_t)q * (uint64_t)(n_class + 1) + (uint64_t)p]++;
+        }
+    }
+}
+
 /* Connected components of the subgraph of the N-cube induced on genotypes of
  * equal (designing) phenotype.  labels[g] = smallest genotype of g's
  * component; 0xFFFFFFFF for deleterious genotypes.  Breadth-first search

@@ -502,3 +502,72 @@ def test_sampled_sequences_are_fair_coin_flips():
     assert len(np.unique(seqs)) >= n - 2
     other = oracle.sample_sequences(1, 0, 1 << 10, N)
     assert not np.array_equal(other, seqs[:1 << 10])
+
+
+# --------------------------------------------------------------------------
+# The full phi_pq matrix (Eq. 2 for every pair of phenotypes)
+# --------------------------------------------------------------------------
+
+def test_phi_counts_hand_example():
+    # N = 2: genotypes 0, 1, 2, 3 with phenotypes q0, q0, q1, deleterious.
+    # 0 -> {1: q0, 2: q1}; 1 -> {0: q0, 3: del}; 2 -> {3: del, 0: q0}.
+    c = oracle.phi_counts(2, np.array([0, 0, 1, NONE], np.uint16), 2)
+    assert c.tolist() == [[2, 1, 1], [1, 0, 1]]
+    # an id that is not a phenotype (5 >= n_class) has no row and counts as
+    # a deleterious mutant
+    c = oracle.phi_counts(2, np.array([0, 5, 1, NONE], np.uint16), 2)
+    assert c.tolist() == [[0, 1, 1], [1, 0, 1]]
+
+
+@pytest.mark.parametrize("N", [1, 5, 10])
+def test_phi_counts_closed_forms(N):
+    n = 1 << N
+    # one phenotype everywhere: every mutation is neutral
+    c = oracle.phi_counts(N, np.zeros(n, np.uint16), 1)
+    assert c.tolist() == [[N * n, 0]]
+    # nothing folds: no rows carry counts
+    assert not oracle.phi_counts(N, np.full(n, NONE, np.uint16), 3).any()
+    # phenotype = parity of the number of H: every mutation flips it
+    par = np.array([bin(g).count("1") & 1 for g in range(n)], np.uint16)
+    c = oracle.phi_counts(N, par, 2)
+    assert c.tolist() == [[0, N * n // 2, 0], [N * n // 2, 0, 0]]
+
+
+def test_phi_counts_brute_force_random_maps():
+    rng = np.random.default_rng(11)
+    for N, n_class in ((4, 3), (7, 5), (8, 40)):
+        # ids beyond n_class and the deleterious id mixed in
+        phen = rng.integers(0, n_class + 2, 1 << N).astype(np.uint16)
+        phen[rng.random(1 << N) < 0.3] = NONE
+        want = {}
+        for g in range(1 << N):
+            if phen[g] >= n_class:
+                continue
+            for i in range(N):
+                p = int(phen[g ^ (1 << i)])
+                key = (int(phen[g]), p if p < n_class else n_class)
+                want[key] = want.get(key, 0) + 1
+        got = oracle.phi_counts(N, phen, n_class)
+        assert got.shape == (n_class, n_class + 1)
+        nz = {(int(q), int(p)): int(got[q, p]) for q, p in zip(*np.nonzero(got))}
+        assert nz == want
+
+
+@pytest.mark.parametrize("dims", [(2, 3, 1), (3, 3, 1), (4, 4, 1), (2, 2, 3)])
+def test_phi_counts_invariants(dims):
+    st = oracle.structures(*dims)
+    gs = oracle.ground_states(st)
+    n = st.n_class
+    c = oracle.phi_counts(st.N, gs.out, n)
+    nb = oracle.neighbors(st.N, gs.out, n)
+    # a single-point mutation is its own inverse: q -> p links equal p -> q links
+    assert np.array_equal(c[:, :n], c[:, :n].T)
+    # every genotype of q has N mutants
+    assert np.array_equal(c.sum(axis=1), st.N * gs.designability.astype(np.uint64))
+    # the diagonal is the robustness numerator, the last column phi_del's
+    assert np.array_equal(np.diag(c[:, :n]), nb.neutral)
+    assert np.array_equal(c[:, n], nb.deleterious)
+    assert np.array_equal(c[:, :n].sum(axis=1) - np.diag(c[:, :n]), nb.other)
+    for q in range(n):
+        row = oracle.neighbors(st.N, gs.out, n, phi_q=q).phi_row
+        assert np.array_equal(c[q], row)
