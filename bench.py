@@ -254,7 +254,8 @@ def recorded_traffic(kname):
 
 
 def extra_measurements(hp, s, ws, dev, blocked_map):
-    """The dense int8 form over the same full 3x3x3 map (its fraction of the
+    """The whole phi_pq matrix of the full 3x3x3 map (dense counts and
+    compressed rows), the dense int8 form over the same full 3x3x3 map (its fraction of the
     int8 MFMA peak, and a bit-exact comparison with the blocked form's map),
     the popcount form on a 2^24 slice, the sampling mode on both lattices, and
     one 2^28 block of the 6x6 map in all three forms with the full 6x6 time
@@ -263,6 +264,27 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
     res = {}
     t = Timer()
     total = 1 << s.N
+    # the whole phi_pq matrix of the map (Eq. 2): dense counts, then
+    # compressed rows
+    n = s.n_class
+    counts = torch.zeros((n, n + 1), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t.start()
+    hp.hp_phi_counts(s, blocked_map, counts)
+    t.stop()
+    torch.cuda.synchronize()
+    res["phi_counts_ms_3x3x3"] = t.ms()
+    rp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    t0 = time.perf_counter()
+    nnz = hp.hp_phi_sparse(s, counts, rp)
+    cols = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    vals = torch.empty(max(nnz, 1), dtype=torch.int64, device=dev)
+    hp.hp_phi_sparse(s, counts, rp, cols, vals)
+    torch.cuda.synchronize()
+    res["phi_sparse_ms_3x3x3"] = (time.perf_counter() - t0) * 1e3
+    res["phi_matrix_nnz_3x3x3"] = nnz
+    res["phi_matrix_dense_bytes_3x3x3"] = counts.numel() * 8
+    del counts, cols, vals, rp
     dense = torch.empty(total, dtype=torch.int16, device=dev)
     hp.hp_enumerate(s, ws, hp.FORM_GEMM_I8, 0, 1 << 16, dense)
     torch.cuda.synchronize()

@@ -377,6 +377,38 @@ hp_status hp_neighbors(const hp_structs *s, const uint16_t *d_map, uint64_t *d_n
                        uint64_t *d_phi_row, void *stream);
 
 /*
+ * hp_phi_counts -- the whole phi_pq matrix of Eq. 2 (every pair of
+ * phenotypes, not one row) as counts.  d_map holds the phenotype of all 2^N
+ * sequences.  d_counts is a row-major uint64 matrix of n_class rows and
+ * n_class + 1 columns owned by the caller (n_class (n_class + 1) 8 bytes:
+ * 21.4 GB for the 51704 classes of 3x3x3, 6.6 GB for 6x6).  For every
+ * genotype g of phenotype q < n_class and each of its N one-bit mutants of
+ * phenotype p: d_counts[q (n_class + 1) + p] += 1, with p replaced by
+ * n_class when it is HP_NONE or not below n_class (deleterious).  Hence
+ * phi_pq = counts[q][p] / (N N_q), the diagonal is the robustness numerator,
+ * column n_class the numerator of phi_del, and row q equals the d_phi_row
+ * of hp_neighbors with phi_q = q.  Counts accumulate: zero the matrix first.
+ * Asynchronous on `stream`.
+ * Errors: HP_EINVAL for a NULL handle, map or matrix; HP_EDEVICE.
+ *
+ * hp_phi_sparse -- compressed rows of such a matrix: d_row_ptr (n_class + 1
+ * uint64, caller-owned) receives the row offsets, d_cols (uint32) and d_vals
+ * (uint64) the non-zero entries of each row in ascending column order, up to
+ * `capacity` entries.  *nnz (may be NULL) receives the number of non-zero
+ * entries.  With d_cols and d_vals both NULL only d_row_ptr and *nnz are
+ * produced (a size query).  Synchronises `stream` once to read the count,
+ * so it cannot be captured into a graph.
+ * Errors: HP_EINVAL for a NULL handle, matrix or row_ptr, or only one of
+ * d_cols / d_vals NULL; HP_ERANGE when capacity < nnz (nothing written
+ * beyond d_row_ptr); HP_EDEVICE.
+ */
+hp_status hp_phi_counts(const hp_structs *s, const uint16_t *d_map, uint64_t *d_counts,
+                        void *stream);
+hp_status hp_phi_sparse(const hp_structs *s, const uint64_t *d_counts, uint64_t *d_row_ptr,
+                        uint32_t *d_cols, uint64_t *d_vals, uint64_t capacity, uint64_t *nnz,
+                        void *stream);
+
+/*
  * hp_components -- neutral networks: connected components of the subgraph
  * of the N-cube of sequences (edges = single point mutations) induced on
  * genotypes of equal designing phenotype (Introduction, "spaghetti vs plum

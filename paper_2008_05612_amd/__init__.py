@@ -32,6 +32,8 @@ from ._binding import (  # noqa: F401
     hp_gemm_shapes,
     hp_graph_capture_batch,
     hp_neighbors,
+    hp_phi_counts,
+    hp_phi_sparse,
     hp_sample,
     hp_structures,
     hp_upload,

@@ -92,6 +92,8 @@ def library():
         "hp_graph_launch": (st, [vp, vp]),
         "hp_graph_free": (None, [vp]),
         "hp_neighbors": (st, [vp, vp, vp, vp, vp, i32, vp, vp]),
+        "hp_phi_counts": (st, [vp, vp, vp, vp]),
+        "hp_phi_sparse": (st, [vp, vp, vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
         "hp_components": (st, [vp, vp, vp, vp, vp, vp, vp]),
         "hp_blocked_select": (st, [ctypes.c_int, ctypes.c_int]),
         "hp_autotune_blocked": (st, [vp, vp, u64, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
@@ -413,6 +415,30 @@ def hp_neighbors(s: Structures, phen_map, neutral=None, deleterious=None, other=
         _ptr(other, torch.int64, s.n_class, "other"), phi_q,
         _ptr(phi_row, torch.int64, s.n_class + 1, "phi_row"), _stream_handle(stream)),
         "hp_neighbors")
+
+
+def hp_phi_counts(s: Structures, phen_map, counts, stream=None):
+    """Add the phi_pq numerators of every phenotype pair to `counts`, an int64
+    device tensor of n_class x (n_class + 1) (last column: deleterious)."""
+    import torch
+    _check(library().hp_phi_counts(
+        s.handle, _ptr(phen_map, _U16, 1 << s.N, "map"),
+        _ptr(counts, torch.int64, s.n_class * (s.n_class + 1), "counts"),
+        _stream_handle(stream)), "hp_phi_counts")
+
+
+def hp_phi_sparse(s: Structures, counts, row_ptr, cols=None, vals=None, stream=None) -> int:
+    """Compressed rows of a counts matrix; returns the number of non-zero
+    entries.  cols (int32) / vals (int64) None: size query only."""
+    import torch
+    cap = 0 if cols is None else min(cols.numel(), vals.numel() if vals is not None else 0)
+    nnz = ctypes.c_uint64(0)
+    _check(library().hp_phi_sparse(
+        s.handle, _ptr(counts, torch.int64, s.n_class * (s.n_class + 1), "counts"),
+        _ptr(row_ptr, torch.int64, s.n_class + 1, "row_ptr"), _ptr(cols, torch.int32, None, "cols"),
+        _ptr(vals, torch.int64, None, "vals"), cap, ctypes.byref(nnz), _stream_handle(stream)),
+        "hp_phi_sparse")
+    return int(nnz.value)
 
 
 def hp_components(s: Structures, phen_map, labels, compsize, ncomp=None, largest=None,

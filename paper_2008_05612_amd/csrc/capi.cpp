@@ -620,6 +620,47 @@ hp_status hp_neighbors(const hp_structs *s, const uint16_t *d_map, uint64_t *d_n
     return e == hipSuccess ? HP_OK : device_fail(e, "hp_neighbors launch");
 }
 
+hp_status hp_phi_counts(const hp_structs *s, const uint16_t *d_map, uint64_t *d_counts,
+                        void *stream)
+{
+    if (!s || !d_map || !d_counts)
+        return fail(HP_EINVAL, "NULL structures, map or counts");
+    hipError_t e = launch_phi_counts(d_map, s->N, int(s->n_class),
+                                     reinterpret_cast<unsigned long long *>(d_counts),
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HP_OK : device_fail(e, "hp_phi_counts launch");
+}
+
+hp_status hp_phi_sparse(const hp_structs *s, const uint64_t *d_counts, uint64_t *d_row_ptr,
+                        uint32_t *d_cols, uint64_t *d_vals, uint64_t capacity, uint64_t *nnz,
+                        void *stream)
+{
+    if (!s || !d_counts || !d_row_ptr)
+        return fail(HP_EINVAL, "NULL structures, counts or row_ptr");
+    if ((d_cols == nullptr) != (d_vals == nullptr))
+        return fail(HP_EINVAL, "give both cols and vals, or neither for a size query");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const auto *counts = reinterpret_cast<const unsigned long long *>(d_counts);
+    const int n_class = int(s->n_class);
+    hipError_t e = launch_phi_row_ptr(counts, n_class, d_row_ptr, st);
+    if (e != hipSuccess)
+        return device_fail(e, "hp_phi_sparse row counts");
+    uint64_t total = 0;
+    e = hipMemcpyAsync(&total, d_row_ptr + n_class, sizeof(total), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return device_fail(e, "hp_phi_sparse entry count");
+    if (nnz)
+        *nnz = total;
+    if (!d_cols)
+        return HP_OK;
+    if (capacity < total)
+        return fail(HP_ERANGE, "capacity is below the number of non-zero entries");
+    e = launch_phi_compact(counts, n_class, d_row_ptr, d_cols, d_vals, st);
+    return e == hipSuccess ? HP_OK : device_fail(e, "hp_phi_sparse compaction");
+}
+
 hp_status hp_components(const hp_structs *s, const uint16_t *d_map, uint32_t *d_labels,
                         uint32_t *d_compsize, uint32_t *d_ncomp, uint32_t *d_largest,
                         void *stream)

@@ -102,6 +102,13 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, uint
 hipError_t launch_neighbors(const uint16_t *map, int N, int n_class, unsigned long long *neutral,
                             unsigned long long *deleterious, unsigned long long *other, int phi_q,
                             unsigned long long *phi_row, hipStream_t st);
+hipError_t launch_phi_counts(const uint16_t *map, int N, int n_class, unsigned long long *counts,
+                             hipStream_t st);
+hipError_t launch_phi_row_ptr(const unsigned long long *counts, int n_class, uint64_t *row_ptr,
+                              hipStream_t st);
+hipError_t launch_phi_compact(const unsigned long long *counts, int n_class,
+                              const uint64_t *row_ptr, uint32_t *cols, uint64_t *vals,
+                              hipStream_t st);
 hipError_t launch_components(const uint16_t *map, int N, uint32_t *labels, uint32_t *compsize,
                              uint32_t *ncomp, uint32_t *largest, int n_class, hipStream_t st);
 

@@ -69,6 +69,153 @@ hipError_t launch_neighbors(const uint16_t *map, int N, int n_class, unsigned lo
 }
 
 // ---------------------------------------------------------------------------
+// The whole phi_pq matrix (Eq. 2) as dense counts: row q (phenotype of the
+// genotype, q < n_class), column p (phenotype of its single-point mutant,
+// column n_class for deleterious ids).  Neutral and deleterious mutants of
+// a genotype are summed in registers and added once; each mutant into
+// another phenotype adds one at (q, p).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_phi_counts(const uint16_t *__restrict__ map, int N,
+                                                    uint64_t total, int n_class,
+                                                    unsigned long long *counts)
+{
+    const uint64_t ld = uint64_t(n_class) + 1;
+    for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += uint64_t(gridDim.x) * blockDim.x) {
+        const int q = map[g];
+        if (q >= n_class)   // 0xFFFF and ids beyond n_class have no row
+            continue;
+        unsigned long long *row = counts + uint64_t(q) * ld;
+        unsigned neutral = 0, del = 0;
+        for (int i = 0; i < N; ++i) {
+            const int p = map[g ^ (uint64_t(1) << i)];
+            if (p == q)
+                ++neutral;
+            else if (p >= n_class)
+                ++del;
+            else
+                atomicAdd(&row[p], 1ull);
+        }
+        if (neutral)
+            atomicAdd(&row[q], (unsigned long long)neutral);
+        if (del)
+            atomicAdd(&row[n_class], (unsigned long long)del);
+    }
+}
+
+// Sparse rows (CSR, columns ascending).  k_phi_row_nnz: one workgroup per
+// row writes its number of non-zero entries to row_ptr[q].
+__global__ __launch_bounds__(256) void k_phi_row_nnz(const unsigned long long *__restrict__ counts,
+                                                     int n_class, uint64_t *row_ptr)
+{
+    __shared__ unsigned part[4];
+    const uint64_t ld = uint64_t(n_class) + 1;
+    const unsigned long long *row = counts + uint64_t(blockIdx.x) * ld;
+    unsigned c = 0;
+    for (uint64_t p = threadIdx.x; p < ld; p += 256)
+        c += row[p] != 0;
+    for (int o = 32; o; o >>= 1)
+        c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        row_ptr[blockIdx.x] = uint64_t(part[0]) + part[1] + part[2] + part[3];
+}
+
+// In-place exclusive scan of row_ptr[0 .. n) with the total written to
+// row_ptr[n]: one workgroup, thread t owns a contiguous chunk.
+__global__ __launch_bounds__(1024) void k_phi_scan(uint64_t *row_ptr, int n)
+{
+    __shared__ uint64_t sums[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int lo = min(n, t * per), hi = min(n, lo + per);
+    uint64_t s = 0;
+    for (int i = lo; i < hi; ++i)
+        s += row_ptr[i];
+    sums[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan of the chunk sums
+        const uint64_t v = t >= off ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    uint64_t run = t ? sums[t - 1] : 0;
+    for (int i = lo; i < hi; ++i) {
+        const uint64_t c = row_ptr[i];
+        row_ptr[i] = run;
+        run += c;
+    }
+    if (t == 1023)
+        row_ptr[n] = sums[1023];
+}
+
+// One workgroup per row: the non-zero entries in column order, placed by
+// wave ballots, at row_ptr[q] onwards.
+__global__ __launch_bounds__(256) void k_phi_compact(const unsigned long long *__restrict__ counts,
+                                                     int n_class, const uint64_t *__restrict__ row_ptr,
+                                                     uint32_t *cols, uint64_t *vals)
+{
+    __shared__ unsigned wave_n[4];
+    const uint64_t ld = uint64_t(n_class) + 1;
+    const unsigned long long *row = counts + uint64_t(blockIdx.x) * ld;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t at = row_ptr[blockIdx.x];
+    for (uint64_t base = 0; base < ld; base += 256) {
+        const uint64_t p = base + threadIdx.x;
+        const unsigned long long v = p < ld ? row[p] : 0;
+        const unsigned long long m = __ballot(v != 0);
+        const unsigned before = __popcll(m & ((1ull << lane) - 1));
+        if (lane == 0)
+            wave_n[wave] = __popcll(m);
+        __syncthreads();
+        unsigned off = 0, tot = 0;
+        for (int w = 0; w < 4; ++w) {
+            off += w < wave ? wave_n[w] : 0;
+            tot += wave_n[w];
+        }
+        if (v) {
+            cols[at + off + before] = uint32_t(p);
+            vals[at + off + before] = v;
+        }
+        at += tot;
+        __syncthreads();   // wave_n is rewritten by the next chunk
+    }
+}
+
+hipError_t launch_phi_counts(const uint16_t *map, int N, int n_class, unsigned long long *counts,
+                             hipStream_t st)
+{
+    const uint64_t total = uint64_t(1) << N;
+    hipLaunchKernelGGL(k_phi_counts, dim3(grid_for(total, 256)), dim3(256), 0, st, map, N, total,
+                       n_class, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_row_ptr(const unsigned long long *counts, int n_class, uint64_t *row_ptr,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_phi_row_nnz, dim3(n_class), dim3(256), 0, st, counts, n_class, row_ptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_phi_scan, dim3(1), dim3(1024), 0, st, row_ptr, n_class);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_compact(const unsigned long long *counts, int n_class,
+                              const uint64_t *row_ptr, uint32_t *cols, uint64_t *vals,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_phi_compact, dim3(n_class), dim3(256), 0, st, counts, n_class, row_ptr,
+                       cols, vals);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Union-find.  parent[x] <= x always holds and roots satisfy parent[x] == x;
 // two roots are joined by pointing the larger at the smaller with a CAS, so
 // the root of every tree is its smallest member and the final labels do not

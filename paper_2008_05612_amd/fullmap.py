@@ -1,7 +1,7 @@
 """Full genotype-phenotype map of one lattice, streamed in sequence blocks.
 
     python -m paper_2008_05612_amd.fullmap --lattice 6x6 [--form blocked|gemm|popcount]
-        [--symmetric] [--block-bits 30] [--neighbors] [--checkpoint FILE] [--json OUT]
+        [--symmetric] [--block-bits 30] [--neighbors] [--phi] [--checkpoint FILE] [--json OUT]
 
 Every step of 2^block_bits sequences is one library call; a progress line is
 printed per step.  The default form is the block-factorised int8 form where
@@ -14,10 +14,14 @@ indices.  The uint16 map stays resident on the device (2^36 x 2 B = 137 GB
 for 6x6) unless --no-map is given.  With --checkpoint, the accumulated
 designability is written after every step and a rerun resumes after the last
 finished step (the map of skipped steps is then not available, so
---neighbors is refused on a resumed run).
+--neighbors is refused on a resumed run).  --phi builds the whole phi_pq
+matrix of Eq. 2 (dense counts on the device, n_class (n_class + 1) 8 bytes,
+then compressed rows) and reports its size, its symmetry check and the
+connected components of the phenotype graph (designable phenotypes joined
+when a single mutation links them).
 
 All device work goes through the C ABI (hp_enumerate, hp_enumerate_symmetric,
-hp_enumerate_symmetric_blocked, hp_neighbors).
+hp_enumerate_symmetric_blocked, hp_neighbors, hp_phi_counts, hp_phi_sparse).
 """
 from __future__ import annotations
 
@@ -59,7 +63,8 @@ def _save_checkpoint(path, dims, form, block_bits, symmetric, next_block, desig,
 
 
 def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
-        checkpoint=None, progress=print, device="cuda", symmetric=False, table=None):
+        checkpoint=None, progress=print, device="cuda", symmetric=False, table=None,
+        phi=False):
     """Enumerate all 2^N sequences of the box; returns a summary dict (and the
     device map under key "map" when keep_map)."""
     import numpy as np
@@ -90,8 +95,9 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
         start_block = ck["next_block"]
         desig.copy_(torch.tensor(np.array(ck["designability"], dtype=np.uint64).view(np.int64)))
         nond.fill_(ck["nondesign"])
-        if neighbors and start_block > 0:
-            raise ValueError("neighbour counts need the whole map; resume without --neighbors")
+        if (neighbors or phi) and start_block > 0:
+            raise ValueError("neighbour counts need the whole map; resume without "
+                             "--neighbors / --phi")
         progress("resuming at block %d of %d" % (start_block, n_blocks))
     out = torch.empty(total, dtype=torch.int16, device=device) if keep_map else None
     t0 = time.time()
@@ -149,11 +155,58 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
         summary["isolated_phenotypes"] = int((oth_h[des] == 0).sum())
         summary["phenotypes_connected_to_top"] = int((row[:s.n_class].cpu().numpy() > 0).sum())
         summary["_counts"] = (neu_h, dele_h, oth_h)
+    if phi and out is not None:
+        summary.update(_phi_summary(s, out, d, device))
     summary["_designability"] = d
     if out is not None:
         summary["map"] = out
     summary["_structs"] = s
     return summary
+
+
+def _phi_summary(s, out, d, device):
+    """The whole phi_pq matrix of the map: dense counts, compressed rows, the
+    mutation-involution symmetry check and the phenotype graph's components."""
+    import numpy as np
+    import torch
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    n = s.n_class
+    counts = torch.zeros((n, n + 1), dtype=torch.int64, device=device)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    hp.hp_phi_counts(s, out, counts)
+    torch.cuda.synchronize()
+    t_counts = time.time() - t0
+    sq = counts[:, :n]
+    symmetric = bool((sq == sq.t()).all().item())
+    rp = torch.empty(n + 1, dtype=torch.int64, device=device)
+    t0 = time.time()
+    nnz = hp.hp_phi_sparse(s, counts, rp)
+    cols = torch.empty(max(nnz, 1), dtype=torch.int32, device=device)
+    vals = torch.empty(max(nnz, 1), dtype=torch.int64, device=device)
+    hp.hp_phi_sparse(s, counts, rp, cols, vals)
+    torch.cuda.synchronize()
+    t_sparse = time.time() - t0
+    del counts, sq
+    rp_h = rp.cpu().numpy()
+    p = cols[:nnz].cpu().numpy().astype(np.int64)
+    q = np.repeat(np.arange(n), np.diff(rp_h))
+    off = (p != q) & (p != n)
+    des = d > 0
+    g = coo_matrix((np.ones(int(off.sum()), np.int8), (q[off], p[off])), shape=(n, n)).tocsr()
+    ncomp, lab = connected_components(g, directed=False)
+    sizes = np.bincount(lab[des], minlength=ncomp)
+    sizes = sizes[sizes > 0]
+    return {
+        "phi_counts_s": t_counts, "phi_sparse_s": t_sparse, "phi_nnz": int(nnz),
+        "phi_dense_bytes": n * (n + 1) * 8, "phi_symmetric": symmetric,
+        "phi_offdiag_links": int(off.sum()),
+        "phenotype_graph_components": int(len(sizes)),
+        "phenotype_graph_largest_component": int(sizes.max()) if len(sizes) else 0,
+        "phenotype_graph_isolated": int((sizes == 1).sum()),
+    }
 
 
 def main(argv=None):
@@ -163,6 +216,7 @@ def main(argv=None):
     ap.add_argument("--block-bits", type=int, default=30)
     ap.add_argument("--symmetric", action="store_true")
     ap.add_argument("--neighbors", action="store_true")
+    ap.add_argument("--phi", action="store_true")
     ap.add_argument("--no-map", action="store_true")
     ap.add_argument("--checkpoint")
     ap.add_argument("--json")
@@ -170,7 +224,7 @@ def main(argv=None):
     form = {None: None, "blocked": hp.FORM_BLOCKED_I8, "gemm": hp.FORM_GEMM_I8,
             "popcount": hp.FORM_POPCOUNT}[a.form]
     res = run(_parse_lattice(a.lattice), form, a.block_bits, keep_map=not a.no_map,
-              neighbors=a.neighbors, checkpoint=a.checkpoint,
+              neighbors=a.neighbors, phi=a.phi, checkpoint=a.checkpoint,
               progress=lambda m: print(m, flush=True), symmetric=a.symmetric)
     pub = {k: v for k, v in res.items() if not k.startswith("_") and k != "map"}
     line = json.dumps(pub)

@@ -119,6 +119,15 @@ def test_argument_errors(lib):
     assert lib.hp_neighbors(s.handle, None, None, None, None, -1, None, None) == -1
     assert lib.hp_neighbors(s.handle, fake_ws, None, None, None, s.n_class, None, None) == -1
     assert lib.hp_components(s.handle, fake_ws, None, None, None, None, None) == -1
+    # phi matrix: NULL handle, map, matrix or row_ptr; cols without vals
+    assert lib.hp_phi_counts(None, fake_ws, fake_ws, None) == -1
+    assert lib.hp_phi_counts(s.handle, None, fake_ws, None) == -1
+    assert lib.hp_phi_counts(s.handle, fake_ws, None, None) == -1
+    assert lib.hp_phi_sparse(None, fake_ws, fake_ws, None, None, 0, None, None) == -1
+    assert lib.hp_phi_sparse(s.handle, None, fake_ws, None, None, 0, None, None) == -1
+    assert lib.hp_phi_sparse(s.handle, fake_ws, None, None, None, 0, None, None) == -1
+    assert lib.hp_phi_sparse(s.handle, fake_ws, fake_ws, fake_ws, None, 8, None, None) == -1
+    assert lib.hp_phi_sparse(s.handle, fake_ws, fake_ws, None, fake_ws, 8, None, None) == -1
     big = hp.Structures(6, 6, 1)
     assert lib.hp_components(big.handle, fake_ws, fake_ws, fake_ws, None, None, None) == -4
     # energy-gap threshold outside 1 .. 255; sampling: empty draw range, idx_hi > 2^48

@@ -56,7 +56,7 @@ def hp1996_map():
     hp.hp_neighbors(s, out, neu, dele, oth, top, row)
     torch.cuda.synchronize()
     u = lambda t: t.cpu().numpy().view(np.uint64)  # noqa: E731
-    return s, desig, int(nd.item()), top, u(neu), u(dele), u(oth), u(row)
+    return s, desig, int(nd.item()), top, u(neu), u(dele), u(oth), u(row), out
 
 
 def _near(name, got, gold):
@@ -86,7 +86,7 @@ def test_counts_match_the_paper(hp1996_map):
 
 
 def test_neighbourhood_statistics_match_the_paper(hp1996_map):
-    s, desig, nondes, top, neu, dele, oth, row = hp1996_map
+    s, desig, nondes, top, neu, dele, oth, row, _ = hp1996_map
     g = _golden()
     N = 27
     des = desig > 0
@@ -107,3 +107,53 @@ def test_neighbourhood_statistics_match_the_paper(hp1996_map):
     _near("isolated_percent", 100.0 * iso / float(des.sum()), g)
     _near("mean_other_percent", 100.0 * float((oth[des] / (N * nq)).mean()), g)
     _near("connected_percent", 100.0 * (1 - iso / float(des.sum())), g)
+
+
+def test_full_phi_matrix_matches_the_paper(hp1996_map):
+    """All 51704 x 51705 counts of Eq. 2 (21.4 GB dense on the device), then
+    compressed rows: the paper's neighbourhood numbers and the invariants of
+    the whole matrix."""
+    import torch
+    s, desig, nondes, top, neu, dele, oth, row, out = hp1996_map
+    g = _golden()
+    n, N = s.n_class, 27
+    c = torch.zeros((n, n + 1), dtype=torch.int64, device="cuda")
+    print("phi matrix %d x %d" % (n, n + 1), flush=True)
+    hp.hp_phi_counts(s, out, c)
+    rp = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    nnz = hp.hp_phi_sparse(s, c, rp)
+    cols = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    vals = torch.empty(nnz, dtype=torch.int64, device="cuda")
+    hp.hp_phi_sparse(s, c, rp, cols, vals)
+    top_dense = c[top].cpu().numpy().view(np.uint64)
+    del c
+    torch.cuda.synchronize()
+    rp = rp.cpu().numpy().astype(np.int64)
+    p = cols.cpu().numpy().astype(np.int64)
+    v = vals.cpu().numpy().view(np.uint64)
+    q = np.repeat(np.arange(n), np.diff(rp))
+    print("non-zero entries %d" % nnz, flush=True)
+    # the row of the top fold is hp_neighbors' phi row
+    assert np.array_equal(top_dense, row)
+    # every genotype has N mutants; diagonal, deleterious column and the rest
+    assert np.array_equal(np.bincount(q, weights=v, minlength=n).astype(np.uint64),
+                          N * desig.astype(np.uint64))
+    diag = q == p
+    assert np.array_equal(np.bincount(q[diag], weights=v[diag], minlength=n).astype(np.uint64), neu)
+    dcol = p == n
+    assert np.array_equal(np.bincount(q[dcol], weights=v[dcol], minlength=n).astype(np.uint64),
+                          dele)
+    off = ~diag & ~dcol
+    assert np.array_equal(np.bincount(q[off], weights=v[off], minlength=n).astype(np.uint64), oth)
+    # single-point mutation is an involution: the q -> p and p -> q links match
+    k1 = q[off] * n + p[off]
+    k2 = p[off] * n + q[off]
+    o2 = np.argsort(k2, kind="stable")
+    assert np.array_equal(k1, k2[o2]) and np.array_equal(v[off], v[off][o2])
+    # the paper's numbers, now read from the whole matrix
+    des = desig > 0
+    linked = np.bincount(q[off], minlength=n) > 0
+    iso = int((des & ~linked).sum())
+    _near("isolated_phenotypes", iso, g)
+    _near("connected_percent", 100.0 * (1 - iso / float(des.sum())), g)
+    _near("connected_to_top_percent", 100.0 * int((q[off] == top).sum()) / float(des.sum()), g)
