@@ -104,8 +104,14 @@ __global__ __launch_bounds__(256) void k_phi_counts(const uint16_t *__restrict__
     }
 }
 
-// Sparse rows (CSR, columns ascending).  k_phi_row_nnz: one workgroup per
-// row writes its number of non-zero entries to row_ptr[q].
+// Sparse rows (CSR, columns ascending).  Both passes stream the dense
+// matrix once (HBM-bound); each thread keeps kPhiUnroll loads in flight, a
+// workgroup covers kPhiChunk consecutive columns per iteration.
+constexpr int kPhiUnroll = 4;
+constexpr int kPhiChunk = 256 * kPhiUnroll;
+
+// k_phi_row_nnz: one workgroup per row writes its number of non-zero
+// entries to row_ptr[q].
 __global__ __launch_bounds__(256) void k_phi_row_nnz(const unsigned long long *__restrict__ counts,
                                                      int n_class, uint64_t *row_ptr)
 {
@@ -113,8 +119,17 @@ __global__ __launch_bounds__(256) void k_phi_row_nnz(const unsigned long long *_
     const uint64_t ld = uint64_t(n_class) + 1;
     const unsigned long long *row = counts + uint64_t(blockIdx.x) * ld;
     unsigned c = 0;
-    for (uint64_t p = threadIdx.x; p < ld; p += 256)
-        c += row[p] != 0;
+    for (uint64_t base = 0; base < ld; base += kPhiChunk) {
+        unsigned long long v[kPhiUnroll];
+#pragma unroll
+        for (int k = 0; k < kPhiUnroll; ++k) {
+            const uint64_t p = base + k * 256 + threadIdx.x;
+            v[k] = p < ld ? row[p] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kPhiUnroll; ++k)
+            c += v[k] != 0;
+    }
     for (int o = 32; o; o >>= 1)
         c += __shfl_xor(c, o);
     if ((threadIdx.x & 63) == 0)
@@ -153,35 +168,52 @@ __global__ __launch_bounds__(1024) void k_phi_scan(uint64_t *row_ptr, int n)
         row_ptr[n] = sums[1023];
 }
 
-// One workgroup per row: the non-zero entries in column order, placed by
-// wave ballots, at row_ptr[q] onwards.
+// One workgroup per row: the non-zero entries in column order, from
+// row_ptr[q] onwards.  Sub-chunk k of a chunk holds columns base + 256 k ..
+// base + 256 k + 255 (thread t reads column base + 256 k + t); an entry's
+// slot is the count of non-zeros in earlier sub-chunks, earlier waves of its
+// sub-chunk (per-wave counts in LDS) and earlier lanes of its wave (ballot).
 __global__ __launch_bounds__(256) void k_phi_compact(const unsigned long long *__restrict__ counts,
                                                      int n_class, const uint64_t *__restrict__ row_ptr,
                                                      uint32_t *cols, uint64_t *vals)
 {
-    __shared__ unsigned wave_n[4];
+    __shared__ unsigned wave_n[kPhiUnroll][4];
     const uint64_t ld = uint64_t(n_class) + 1;
     const unsigned long long *row = counts + uint64_t(blockIdx.x) * ld;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1;
     uint64_t at = row_ptr[blockIdx.x];
-    for (uint64_t base = 0; base < ld; base += 256) {
-        const uint64_t p = base + threadIdx.x;
-        const unsigned long long v = p < ld ? row[p] : 0;
-        const unsigned long long m = __ballot(v != 0);
-        const unsigned before = __popcll(m & ((1ull << lane) - 1));
-        if (lane == 0)
-            wave_n[wave] = __popcll(m);
+    for (uint64_t base = 0; base < ld; base += kPhiChunk) {
+        unsigned long long v[kPhiUnroll];
+        unsigned before[kPhiUnroll];
+#pragma unroll
+        for (int k = 0; k < kPhiUnroll; ++k) {
+            const uint64_t p = base + k * 256 + threadIdx.x;
+            v[k] = p < ld ? row[p] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kPhiUnroll; ++k) {
+            const unsigned long long m = __ballot(v[k] != 0);
+            before[k] = __popcll(m & below);
+            if (lane == 0)
+                wave_n[k][wave] = __popcll(m);
+        }
         __syncthreads();
-        unsigned off = 0, tot = 0;
-        for (int w = 0; w < 4; ++w) {
-            off += w < wave ? wave_n[w] : 0;
-            tot += wave_n[w];
+        unsigned run = 0;
+#pragma unroll
+        for (int k = 0; k < kPhiUnroll; ++k) {
+            unsigned off = 0;
+            for (int w = 0; w < 4; ++w) {
+                off += w < wave ? wave_n[k][w] : 0;
+            }
+            if (v[k]) {
+                const uint64_t slot = at + run + off + before[k];
+                cols[slot] = uint32_t(base + k * 256 + threadIdx.x);
+                vals[slot] = v[k];
+            }
+            run += wave_n[k][0] + wave_n[k][1] + wave_n[k][2] + wave_n[k][3];
         }
-        if (v) {
-            cols[at + off + before] = uint32_t(p);
-            vals[at + off + before] = v;
-        }
-        at += tot;
+        at += run;
         __syncthreads();   // wave_n is rewritten by the next chunk
     }
 }

@@ -1,7 +1,8 @@
 """Full genotype-phenotype map of one lattice, streamed in sequence blocks.
 
     python -m paper_2008_05612_amd.fullmap --lattice 6x6 [--form blocked|gemm|popcount]
-        [--symmetric] [--block-bits 30] [--neighbors] [--phi] [--checkpoint FILE] [--json OUT]
+        [--symmetric] [--block-bits 30] [--neighbors] [--phi] [--table E_PP,E_PH,E_HP,E_HH]
+        [--checkpoint FILE] [--json OUT]
 
 Every step of 2^block_bits sequences is one library call; a progress line is
 printed per step.  The default form is the block-factorised int8 form where
@@ -42,22 +43,25 @@ def _parse_lattice(text: str):
     return tuple(dims)
 
 
-def _load_checkpoint(path, dims, form, block_bits, n_class, symmetric):
+def _load_checkpoint(path, dims, form, block_bits, n_class, symmetric, table):
     if not path or not os.path.exists(path):
         return None
     with open(path) as f:
         ck = json.load(f)
     if (tuple(ck["dims"]) != dims or ck["form"] != form or ck["block_bits"] != block_bits
-            or len(ck["designability"]) != n_class or ck.get("symmetric", False) != symmetric):
+            or len(ck["designability"]) != n_class or ck.get("symmetric", False) != symmetric
+            or ck.get("table") != (list(table) if table else None)):
         raise ValueError("checkpoint %s is for another run" % path)
     return ck
 
 
-def _save_checkpoint(path, dims, form, block_bits, symmetric, next_block, desig, nondesign):
+def _save_checkpoint(path, dims, form, block_bits, symmetric, table, next_block, desig,
+                     nondesign):
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump({"dims": list(dims), "form": form, "block_bits": block_bits,
-                   "symmetric": symmetric, "next_block": next_block,
+                   "symmetric": symmetric, "table": list(table) if table else None,
+                   "next_block": next_block,
                    "designability": [int(x) for x in desig], "nondesign": int(nondesign)}, f)
     os.replace(tmp, path)
 
@@ -90,7 +94,7 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
     desig = torch.zeros(s.n_class, dtype=torch.int64, device=device)
     nond = torch.zeros(1, dtype=torch.int64, device=device)
     start_block = 0
-    ck = _load_checkpoint(checkpoint, dims, form, block_bits, s.n_class, symmetric)
+    ck = _load_checkpoint(checkpoint, dims, form, block_bits, s.n_class, symmetric, table)
     if ck:
         start_block = ck["next_block"]
         desig.copy_(torch.tensor(np.array(ck["designability"], dtype=np.uint64).view(np.int64)))
@@ -113,7 +117,7 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
                             desig, nond)
         torch.cuda.synchronize()
         if checkpoint:
-            _save_checkpoint(checkpoint, dims, form, block_bits, symmetric, b + 1,
+            _save_checkpoint(checkpoint, dims, form, block_bits, symmetric, table, b + 1,
                              desig.cpu().numpy().view(np.uint64), int(nond.item()))
         progress("block %d/%d [%d, %d) %.2f s" % (b + 1, n_blocks, lo, hi, time.time() - tb))
     wall = time.time() - t0
@@ -217,6 +221,9 @@ def main(argv=None):
     ap.add_argument("--symmetric", action="store_true")
     ap.add_argument("--neighbors", action="store_true")
     ap.add_argument("--phi", action="store_true")
+    ap.add_argument("--table", default=None,
+                    help="two-letter contact energies E_PP,E_PH,E_HP,E_HH (integers; the "
+                         "paper's Table 1 scaled by 10 is 0,-10,-10,-23); default pure HP")
     ap.add_argument("--no-map", action="store_true")
     ap.add_argument("--checkpoint")
     ap.add_argument("--json")
@@ -225,7 +232,8 @@ def main(argv=None):
             "popcount": hp.FORM_POPCOUNT}[a.form]
     res = run(_parse_lattice(a.lattice), form, a.block_bits, keep_map=not a.no_map,
               neighbors=a.neighbors, phi=a.phi, checkpoint=a.checkpoint,
-              progress=lambda m: print(m, flush=True), symmetric=a.symmetric)
+              progress=lambda m: print(m, flush=True), symmetric=a.symmetric,
+              table=tuple(int(x) for x in a.table.split(",")) if a.table else None)
     pub = {k: v for k, v in res.items() if not k.startswith("_") and k != "map"}
     line = json.dumps(pub)
     print(line, flush=True)
