@@ -235,6 +235,9 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+HP1996_X10 = (0, -10, -10, -23)   # Table 1 energies scaled by 10: E_PP, E_PH, E_HP, E_HH
+
+
 def recorded_traffic(kname):
     """HBM bytes per full-map launch of `kname`, from the calibrated
     FETCH_SIZE / WRITE_SIZE counter summary of the blocked kernel in
@@ -255,7 +258,9 @@ def recorded_traffic(kname):
 
 def extra_measurements(hp, s, ws, dev, blocked_map):
     """The whole phi_pq matrix of the full 3x3x3 map (dense counts and
-    compressed rows), the dense int8 form over the same full 3x3x3 map (its fraction of the
+    compressed rows), the paper's own timed workload (Table 1 energies,
+    sampled sequences) on 3x3x3 and 6x6, the dense int8 form over the same
+    full 3x3x3 map (its fraction of the
     int8 MFMA peak, and a bit-exact comparison with the blocked form's map),
     the popcount form on a 2^24 slice, the sampling mode on both lattices, and
     one 2^28 block of the 6x6 map in all three forms with the full 6x6 time
@@ -344,6 +349,23 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
         sec = t.ms() * 1e-3
         res["3x3x3_sample_%s_evals_per_s" % name] = nd_ * s.n_conf / sec
         res["3x3x3_sample_%s_s_per_sequence" % name] = sec / nd_
+    # the paper's timed workload itself: Table 1 energies (x10), random
+    # sequences, 2^14 per launch, on both lattices of its CPU/GPU table
+    for dims in ((3, 3, 3), (6, 6, 1)):
+        sh = hp.Structures(*dims, table=HP1996_X10)
+        wsh = sh.workspace()
+        name = "x".join(str(x) for x in dims if x > 1)
+        hp.hp_sample(sh, wsh, hp.FORM_GEMM_I8, 1, 0, 1 << 14, 1)
+        torch.cuda.synchronize()
+        for nd_, tag in ((1 << 14, "2^14"), (1 << 22, "2^22")):
+            t.start()
+            hp.hp_sample(sh, wsh, hp.FORM_GEMM_I8, 0x2008056120, 0, nd_, 1)
+            t.stop()
+            torch.cuda.synchronize()
+            sec = t.ms() * 1e-3
+            res["%s_hp1996_sample_%s_s_per_sequence" % (name, tag)] = sec / nd_
+            res["%s_hp1996_sample_%s_evals_per_s" % (name, tag)] = nd_ * sh.n_conf / sec
+        del wsh, sh
     s6 = hp.Structures(6, 6, 1)
     ws6 = s6.workspace()
     hp.hp_sample(s6, ws6, hp.FORM_GEMM_I8, 1, 0, 1 << 14, 1)
