@@ -406,7 +406,8 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
 
 def cpu_baseline(dims, seconds):
     """The oracle (plain C, OpenMP over sequences) on a bounded window of the
-    same workload, on this host's cores."""
+    same workload, on this host's cores (all threads and one thread), and on
+    a window of the 6x6 map; full-map times extrapolated from the rates."""
     import oracle
     st = oracle.structures(*dims)
     lo = 0
@@ -426,11 +427,27 @@ def cpu_baseline(dims, seconds):
     oracle.ground_states(st, lo, lo + n1)
     dt1 = time.perf_counter() - t0
     oracle.set_num_threads(cores)
-    return {"value": n * st.n_conf / dt, "unit": "evals/s", "cores": cores,
+    # the 6x6 map on a window of at most 2^16 sequences, sized to about 5 s
+    st6 = oracle.structures(6, 6, 1)
+    n6 = 1 << 12
+    t0 = time.perf_counter()
+    oracle.ground_states(st6, 0, n6)
+    dt6 = time.perf_counter() - t0
+    n6 = int(max(1 << 12, min(1 << 16, n6 * 5.0 / max(dt6, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.ground_states(st6, 0, n6)
+    dt6 = time.perf_counter() - t0
+    rate, rate6 = n * st.n_conf / dt, n6 * st6.n_conf / dt6
+    return {"value": rate, "unit": "evals/s", "cores": cores,
             "kind": "oracle",
             "sample": "3x3x3, sequences [0, %d) x all %d conformations, %.1f s" % (n, st.n_conf, dt),
             "value_1_thread": n1 * st.n_conf / dt1,
-            "sample_1_thread": "sequences [0, %d), %.1f s" % (n1, dt1)}
+            "sample_1_thread": "sequences [0, %d), %.1f s" % (n1, dt1),
+            "full_map_s_extrapolated_3x3x3": (1 << st.N) * st.n_conf / rate,
+            "value_6x6": rate6,
+            "sample_6x6": "6x6, sequences [0, %d) x all %d conformations, %.1f s"
+                          % (n6, st6.n_conf, dt6),
+            "full_map_s_extrapolated_6x6": (1 << st6.N) * st6.n_conf / rate6}
 
 
 if __name__ == "__main__":
