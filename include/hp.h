@@ -65,10 +65,13 @@ typedef enum {
  * every monomer above the low 8, so per conformation the energy is a block
  * term plus weights of the 8 low monomers and their mutual contacts; one
  * int8 product per 256 sequences forms those (as bytes), a second product of
- * depth 32 applies them to the sequences.  Needs pure pair energies (a
- * table with E_HP == E_PP, e.g. pure HP), N >= 8 and A * nbp <= 128 (see
- * hp_structs_info: unary_rows == 0); only plain ranges (hp_enumerate,
- * hp_enumerate_gap).  Otherwise HP_EUNSUPPORTED.                          */
+ * depth 32 applies them to the sequences.  Two-letter tables (E_HP !=
+ * E_PP) add the unary terms of the outer monomers as a few more per-block
+ * rows.  Needs N >= 8 and weights whose per-block bytes fit int8 within 32
+ * rows, and with unary rows a first product at most 256 deep (pure HP on
+ * every box up to 6x6 and 3x3x3 qualifies, Table 1 up to 3x3x3 but not 6x6;
+ * hp_canonical_block_count is 0 when a handle does not); only plain ranges
+ * (hp_enumerate, hp_enumerate_gap).  Otherwise HP_EUNSUPPORTED.           */
 #define HP_FORM_BLOCKED_I8 2
 
 typedef struct hp_structs hp_structs;

@@ -44,7 +44,7 @@ hp_status check_range(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
 struct BatchPlan {
     std::vector<char> host;   // header + jobs + item starts
     struct Group {
-        int kb, item_lo, item_hi;   // product depth and its items
+        int kb, item_lo, item_hi;   // product depth (blocked: 2 depth + unary flag), its items
     };
     std::vector<Group> groups;
 };
@@ -66,16 +66,19 @@ hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, B
         if (st != HP_OK)
             return st;
         if (blocked && !jobs[i].structs->blk_ok)
-            return fail(HP_EUNSUPPORTED, "the blocked form needs pure pair energies, N >= 8 "
-                                         "and A * nbp <= 128");
+            return fail(HP_EUNSUPPORTED, "the blocked form needs N >= 8, per-block bytes "
+                                         "within int8 and, with unary rows, depth <= 256");
         kb_max = std::max(kb_max, int(jobs[i].structs->K_pad / 32));
     }
     std::vector<int> order(njobs);
     for (int i = 0; i < njobs; ++i)
         order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return jobs[a].structs->K_pad < jobs[b].structs->K_pad;
-    });
+    // blocked jobs group by depth and by whether they carry unary rows
+    auto depth = [&](int i) {
+        const hp_structs *t = jobs[i].structs;
+        return blocked ? 2 * t->blk_KB + (t->blk_coefB != 0 ? 1u : 0u) : t->K_pad / 32;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return depth(a) < depth(b); });
     std::vector<int64_t> start(njobs + 1, 0);
     for (int r = 0; r < njobs; ++r) {
         const hp_job &jb = jobs[order[r]];
@@ -105,7 +108,8 @@ hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, B
         const hp_job &jb = jobs[order[r]];
         ej[r] = make_enum_job(jb.structs, jb.d_ws, jb.seq_lo, jb.seq_hi, jb.d_out, jb.d_emin,
                               jb.d_designability, jb.d_nondesign);
-        const int kb = int(jb.structs->K_pad / 32);
+        const int kb = blocked ? int(2 * jb.structs->blk_KB + (jb.structs->blk_coefB != 0))
+                               : int(jb.structs->K_pad / 32);
         if (plan->groups.empty() || plan->groups.back().kb != kb)
             plan->groups.push_back({kb, int(start[r]), int(start[r])});
         plan->groups.back().item_hi = int(start[r + 1]);
@@ -122,7 +126,8 @@ hipError_t launch_plan(const BatchPlan &plan, int form, void *d_batch_ws, hipStr
         if (g.item_hi <= g.item_lo)
             continue;
         hipError_t e = form == HP_FORM_BLOCKED_I8
-                           ? launch_gemm_blk_batch(d_batch_ws, g.kb, g.item_lo, g.item_hi, st)
+                           ? launch_gemm_blk_batch(d_batch_ws, g.kb >> 1, (g.kb & 1) != 0,
+                                                   g.item_lo, g.item_hi, st)
                            : launch_gemm_batch(d_batch_ws, g.kb, g.item_lo, g.item_hi, st);
         if (e != hipSuccess)
             return e;
@@ -146,6 +151,11 @@ static void set_block_geometry(EnumJob &j, const hp_structs *s, bool canonical)
     for (int n = 0; n < g.npp; ++n)
         j.blk_pp[n / 8] |= uint64_t(g.pa[n] | (g.pb[n] << 4)) << (8 * (n % 8));
     j.blk_npp = g.npp;
+    j.blk_KB = int32_t(s->blk_KB);
+    j.blk_coefB = s->blk_coefB;
+    j.blk_ngroups = s->blk_ngroups[canonical ? 1 : 0];
+    for (int w = 0; w < 3; ++w)
+        j.blk_grp[w] = s->blk_grp[canonical ? 1 : 0][w];
     j.half_bits = canonical ? g.half : s->N / 2;
     j.blk_s2 = j.gemm_b ? reinterpret_cast<const int8_t *>(j.gemm_b) +
                               (s->ws.blk_s2 - s->ws.gemm_b) + (canonical ? 8 * 64 * 16 : 0)
@@ -350,8 +360,8 @@ hp_status run_blocks(const hp_structs *s, const void *d_ws, int form, uint64_t l
         if (o.mode != kSeqPlain)
             return fail(HP_EUNSUPPORTED, "the blocked form scores plain sequence ranges only");
         if (!s->blk_ok)
-            return fail(HP_EUNSUPPORTED, "the blocked form needs pure pair energies, N >= 8 "
-                                         "and A * nbp <= 128");
+            return fail(HP_EUNSUPPORTED, "the blocked form needs N >= 8, per-block bytes "
+                                         "within int8 and, with unary rows, depth <= 256");
     }
     for (uint64_t lo = lo_all; lo < hi_all;) {
         const uint64_t hi = hi_all - lo > kBlockSeqs ? lo + kBlockSeqs : hi_all;
@@ -476,8 +486,8 @@ hp_status hp_enumerate_symmetric_blocked(const hp_structs *s, const void *d_ws, 
     if (!d_ws)
         return fail(HP_EINVAL, "workspace pointer is NULL");
     if (!s->blk_ok)
-        return fail(HP_EUNSUPPORTED, "the blocked form needs pure pair energies, N >= 8 "
-                                     "and A * nbp <= 128");
+        return fail(HP_EUNSUPPORTED, "the blocked form needs N >= 8, per-block bytes "
+                                     "within int8 and, with unary rows, depth <= 256");
     if (b_lo >= b_hi)
         return fail(HP_EINVAL, "empty block range (b_lo >= b_hi)");
     if (b_hi > hp_canonical_block_count(s))

@@ -44,7 +44,9 @@ constexpr int kBlkTiles = (1 << kBlkBits) / 32;   // sequence tiles per block (8
 // packed 8 bits each in j.blk_pos); j.blk_vmask has their bits.  Virtual
 // rows: m = 0 base; 1 .. 8 w_v for v = pos(m - 1); then one row per pair of
 // varying monomers with odd separation >= 3 (j.blk_npp pairs, x-indices a | b << 4
-// packed a byte each in j.blk_pp[]); then the two index bytes; zero beyond.
+// packed a byte each in j.blk_pp[]); then j.blk_ngroups rows of unary terms
+// (two-letter tables: B c_i h_i summed over a group of outer monomers); then
+// the two index bytes; zero beyond.
 // Plain ranges (CANON false) use the low 8 monomers, a geometry known at
 // compile time: pos(x) = x and the pairs kLow8Pairs, the same list the host
 // lays the second product's operand out by.
@@ -71,20 +73,40 @@ __device__ __forceinline__ int blk_npp(const EnumJob &j) { return CANON ? j.blk_
 template <bool CANON>
 __device__ __forceinline__ uint64_t blk_vmask(const EnumJob &j) { return CANON ? j.blk_vmask : 0xffull; }
 
+// Unary group of monomer i (15: none).  Selects, not an indexed read: a
+// runtime index into the job's array would place the job in scratch memory.
+__device__ __forceinline__ int blk_group(const EnumJob &j, int i)
+{
+    const uint64_t w = i < 16 ? j.blk_grp[0] : (i < 32 ? j.blk_grp[1] : j.blk_grp[2]);
+    return int((w >> (4 * (i & 15))) & 15u);
+}
+
 // Stage-one A operand: this lane's virtual row m = lane & 31 over product
 // rows k = 32 kb + 16 half + q of C1, for the block whose outer monomers are
 // the bits of `outer`.
-template <int KB, bool CANON>
+// UNARY: the job has unary-group rows (two-letter tables); compiled apart so
+// that the pure-pair instances keep this fully unrolled loop small enough to
+// stay in registers at every depth.
+template <int KB, bool CANON, bool UNARY>
 __device__ __forceinline__ void blk_v_fragments(const EnumJob &j, uint64_t outer, int m, int half,
                                                 v4i (&vf)[KB])
 {
     const int N = j.N;
     const int coef = j.blk_coef;
+    const int coefB = UNARY ? j.blk_coefB : 0;
     const uint64_t vmask = blk_vmask<CANON>(j);
-    const int row_idx = kRowVV + blk_npp<CANON>(j);
+    const int row_un = kRowVV + blk_npp<CANON>(j);
+    const int row_idx = row_un + (UNARY ? j.blk_ngroups : 0);
+    // unary-group rows (two-letter tables): the outer H monomers of this
+    // lane's group, as a bit mask over monomer positions
+    uint64_t gmask = 0;
+    if (UNARY && m >= row_un && m < row_idx)
+        for (int i = 0; i < N; ++i)
+            if (blk_group(j, i) == m - row_un && ((outer >> i) & 1u) && !((vmask >> i) & 1u))
+                gmask |= uint64_t(1) << i;
     const int wv = m >= kRowW && m < kRowVV ? blk_pos<CANON>(j, m - kRowW) : -1;
     int va = -1, vb = -1;
-    if (m >= kRowVV && m < row_idx) {
+    if (m >= kRowVV && m < row_un) {
         const int pr = blk_pair<CANON>(j, m - kRowVV);
         va = blk_pos<CANON>(j, pr & 15);
         vb = blk_pos<CANON>(j, pr >> 4);
@@ -116,12 +138,16 @@ __device__ __forceinline__ void blk_v_fragments(const EnumJob &j, uint64_t outer
                     const int jj = i + d;
                     const bool out_i = !((vmask >> i) & 1u), out_j = !((vmask >> jj) & 1u);
                     const bool h_i = (outer >> i) & 1u, h_j = (outer >> jj) & 1u;
-                    if (m == 0)
+                    if (m == 0) {
                         v = out_i && out_j && h_i && h_j ? -coef : 0;
-                    else if (m < kRowVV)
+                    } else if (m < kRowVV) {
                         v = (i == wv && out_j && h_j) || (jj == wv && out_i && h_i) ? -coef : 0;
-                    else if (m < row_idx)
+                        v -= i == wv || jj == wv ? coefB : 0;   // B c_v: every contact of v
+                    } else if (m < row_un) {
                         v = i == va && jj == vb ? -coef : 0;
+                    } else if (UNARY && m < row_idx) {
+                        v = -coefB * int(((gmask >> i) & 1u) + ((gmask >> jj) & 1u));
+                    }
                 }
                 word |= (uint32_t(v) & 0xffu) << (8 * bb);
                 ++i;   // next row: next i, or the next run
@@ -261,7 +287,7 @@ enum { kBlkLds = 0, kBlkPipe = 1, kBlkLdsS2 = 2 };
 // canonical jobs: canonical block index).  lds holds the staged C1 tiles,
 // s2lds the stage-two operand (mode kBlkLdsS2).  Starts and ends at a
 // workgroup barrier, so consecutive calls may reuse the LDS.
-template <int KB, int NW, int MODE, bool CANON>
+template <int KB, int NW, int MODE, bool CANON, bool UNARY>
 __device__ __forceinline__ void blk_body(const EnumJob &j, uint64_t blk0, v4i *lds, v4i *s2lds)
 {
     const int lane = threadIdx.x & 63;
@@ -274,7 +300,7 @@ __device__ __forceinline__ void blk_body(const EnumJob &j, uint64_t blk0, v4i *l
     const v4i *__restrict__ B1 = reinterpret_cast<const v4i *>(j.gemm_b);
 
     v4i vf[KB];
-    blk_v_fragments<KB, CANON>(j, outer, col, half, vf);
+    blk_v_fragments<KB, CANON, UNARY>(j, outer, col, half, vf);
     // stage-two B operand: per-sequence indicators, precomputed per geometry
     v4i sf[MODE == kBlkLdsS2 ? 1 : kBlkTiles];
     const v4i *__restrict__ S2 = reinterpret_cast<const v4i *>(j.blk_s2);
@@ -379,18 +405,18 @@ __device__ __forceinline__ void blk_body(const EnumJob &j, uint64_t blk0, v4i *l
     }
 }
 
-template <int KB, int NW, int MODE, bool CANON>
+template <int KB, int NW, int MODE, bool CANON, bool UNARY>
 __global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
 {
     __shared__ v4i lds[(MODE == kBlkPipe ? 3 : 2) * KB * 64];
     __shared__ v4i s2lds[MODE == kBlkLdsS2 ? kBlkTiles * 64 : 1];
     const uint64_t blk0 = (CANON ? j.lo : j.lo >> kBlkBits) + uint64_t(blockIdx.x) * NW;
-    blk_body<KB, NW, MODE, CANON>(j, blk0, lds, s2lds);
+    blk_body<KB, NW, MODE, CANON, UNARY>(j, blk0, lds, s2lds);
 }
 
 // Batched form for jobs of one product depth: workgroup b scores item
 // item_lo + b, NW consecutive blocks of the job whose item range holds it.
-template <int KB, int NW, int MODE>
+template <int KB, int NW, int MODE, bool UNARY>
 __global__ __launch_bounds__(NW * 64) void k_gemm_blk_batch(BatchHeader *hdr, int item_lo)
 {
     __shared__ v4i lds[2 * KB * 64];
@@ -413,15 +439,25 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk_batch(BatchHeader *hdr, in
         lo = __builtin_amdgcn_readfirstlane(lo);
         const EnumJob &j = jobs[lo];
         const uint64_t blk0 = (j.lo >> kBlkBits) + uint64_t(it - start[lo]) * NW;
-        blk_body<KB, NW, MODE, false>(j, blk0, lds, s2lds);
+        blk_body<KB, NW, MODE, false, UNARY>(j, blk0, lds, s2lds);
     }
 }
 
 template <int KB>
-hipError_t launch_blk_batch_kb(BatchHeader *hdr, int item_lo, unsigned grid, hipStream_t st)
+hipError_t launch_blk_batch_kb(BatchHeader *hdr, int item_lo, unsigned grid, bool unary,
+                               hipStream_t st)
 {
     constexpr int MODE = KB <= 6 ? kBlkLdsS2 : kBlkLds;
-    hipLaunchKernelGGL((k_gemm_blk_batch<KB, 4, MODE>), dim3(grid), dim3(256), 0, st, hdr,
+    if constexpr (KB <= kBlkUnaryMaxKB) {
+        if (unary) {
+            hipLaunchKernelGGL((k_gemm_blk_batch<KB, 4, MODE, true>), dim3(grid), dim3(256), 0,
+                               st, hdr, item_lo);
+            return hipGetLastError();
+        }
+    }
+    if (unary)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gemm_blk_batch<KB, 4, MODE, false>), dim3(grid), dim3(256), 0, st, hdr,
                        item_lo);
     return hipGetLastError();
 }
@@ -434,15 +470,37 @@ hipError_t launch_blk_shape(const EnumJob &j, hipStream_t st)
         canon ? j.hi - j.lo : ((j.hi - 1) >> kBlkBits) - (j.lo >> kBlkBits) + 1;
     const dim3 grid(unsigned((n_blocks + NW - 1) / NW));
     if (canon)
-        hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE, true>), grid, dim3(NW * 64), 0, st, j);
+        hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE, true, false>), grid, dim3(NW * 64), 0, st, j);
     else
-        hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE, false>), grid, dim3(NW * 64), 0, st, j);
+        hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE, false, false>), grid, dim3(NW * 64), 0, st, j);
     return hipGetLastError();
+}
+
+// Two-letter tables: one launch shape (4 waves, staging by depth).
+template <int KB>
+hipError_t launch_blk_unary(const EnumJob &j, hipStream_t st)
+{
+    if constexpr (KB > kBlkUnaryMaxKB) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int MODE = KB <= 6 ? kBlkLdsS2 : kBlkLds;
+        const bool canon = j.mode == kSeqCanonical;
+        const uint64_t n_blocks =
+            canon ? j.hi - j.lo : ((j.hi - 1) >> kBlkBits) - (j.lo >> kBlkBits) + 1;
+        const dim3 grid(unsigned((n_blocks + 3) / 4));
+        if (canon)
+            hipLaunchKernelGGL((k_gemm_blk<KB, 4, MODE, true, true>), grid, dim3(256), 0, st, j);
+        else
+            hipLaunchKernelGGL((k_gemm_blk<KB, 4, MODE, false, true>), grid, dim3(256), 0, st, j);
+        return hipGetLastError();
+    }
 }
 
 template <int KB>
 hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
 {
+    if (j.blk_ngroups > 0 || j.blk_coefB != 0)
+        return launch_blk_unary<KB>(j, st);
     if (mode == kBlkLdsS2) {
         switch (nw) {
         case 2: return launch_blk_shape<KB, 2, kBlkLdsS2>(j, st);
@@ -468,24 +526,24 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
 
 uint64_t blk_batch_seqs_per_item() { return uint64_t(4) << kBlkBits; }
 
-hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, int item_lo, int item_hi,
+hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, int item_lo, int item_hi,
                                  hipStream_t st)
 {
     BatchHeader *hdr = static_cast<BatchHeader *>(d_batch_ws);
     const unsigned grid = unsigned(item_hi - item_lo);
     switch (kb) {
-    case 1: return launch_blk_batch_kb<1>(hdr, item_lo, grid, st);
-    case 2: return launch_blk_batch_kb<2>(hdr, item_lo, grid, st);
-    case 3: return launch_blk_batch_kb<3>(hdr, item_lo, grid, st);
-    case 4: return launch_blk_batch_kb<4>(hdr, item_lo, grid, st);
-    case 5: return launch_blk_batch_kb<5>(hdr, item_lo, grid, st);
-    case 6: return launch_blk_batch_kb<6>(hdr, item_lo, grid, st);
-    case 7: return launch_blk_batch_kb<7>(hdr, item_lo, grid, st);
-    case 8: return launch_blk_batch_kb<8>(hdr, item_lo, grid, st);
-    case 9: return launch_blk_batch_kb<9>(hdr, item_lo, grid, st);
-    case 10: return launch_blk_batch_kb<10>(hdr, item_lo, grid, st);
-    case 11: return launch_blk_batch_kb<11>(hdr, item_lo, grid, st);
-    case 12: return launch_blk_batch_kb<12>(hdr, item_lo, grid, st);
+    case 1: return launch_blk_batch_kb<1>(hdr, item_lo, grid, unary, st);
+    case 2: return launch_blk_batch_kb<2>(hdr, item_lo, grid, unary, st);
+    case 3: return launch_blk_batch_kb<3>(hdr, item_lo, grid, unary, st);
+    case 4: return launch_blk_batch_kb<4>(hdr, item_lo, grid, unary, st);
+    case 5: return launch_blk_batch_kb<5>(hdr, item_lo, grid, unary, st);
+    case 6: return launch_blk_batch_kb<6>(hdr, item_lo, grid, unary, st);
+    case 7: return launch_blk_batch_kb<7>(hdr, item_lo, grid, unary, st);
+    case 8: return launch_blk_batch_kb<8>(hdr, item_lo, grid, unary, st);
+    case 9: return launch_blk_batch_kb<9>(hdr, item_lo, grid, unary, st);
+    case 10: return launch_blk_batch_kb<10>(hdr, item_lo, grid, unary, st);
+    case 11: return launch_blk_batch_kb<11>(hdr, item_lo, grid, unary, st);
+    case 12: return launch_blk_batch_kb<12>(hdr, item_lo, grid, unary, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -496,8 +554,8 @@ hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t s
     // which frees registers for a fourth wave per SIMD (measured faster for
     // K_pad <= 160, slower for 320)
     if (mode < 0)
-        mode = j.KB <= 6 ? kBlkLdsS2 : kBlkLds;
-    switch (j.KB) {
+        mode = j.blk_KB <= 6 ? kBlkLdsS2 : kBlkLds;
+    switch (j.blk_KB) {
     case 1: return launch_blk<1>(j, nw, mode, st);
     case 2: return launch_blk<2>(j, nw, mode, st);
     case 3: return launch_blk<3>(j, nw, mode, st);

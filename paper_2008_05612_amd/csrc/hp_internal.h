@@ -22,6 +22,7 @@ constexpr int kTileConf = 32;        // conformations per MFMA tile (rows of A)
 constexpr int kKeyConfBits = 17;
 constexpr uint32_t kMaxConf = (1u << kKeyConfBits) - 1;
 constexpr int kMaxKB = 12;              // product depth K_pad <= 384
+constexpr int kBlkUnaryMaxKB = 8;       // blocked form with unary rows: first-product depth <= 256
 // Block-factorised int8 form: blocks of 2^kBlkBits consecutive sequences
 // share every monomer above the low kBlkBits.
 constexpr int kBlkBits = 8;
@@ -56,7 +57,10 @@ struct hp_structs {
     // 2^blk_shift, windows of blk_win_tiles tiles, stage-one weight blk_coef
     bool blk_ok = false;
     uint32_t blk_shift = 0, blk_win_tiles = 0;
-    int32_t blk_coef = 0;
+    int32_t blk_coef = 0, blk_coefB = 0;   // m2 A, m2 B
+    uint32_t blk_KB = 0;                   // depth of the first product / 32
+    int32_t blk_ngroups[2] = {0, 0};       // unary-term rows per geometry (plain, canonical)
+    uint64_t blk_grp[2][3] = {};           // group id of each outer monomer, 4 bits, 15 = none
     std::vector<uint8_t> walks;       // n_conf * N canonical site sequences, ascending
     std::vector<uint16_t> c2q;        // conformation -> class
     std::vector<uint32_t> rev_conf;   // conformation of the reversed chain

@@ -38,6 +38,8 @@ struct EnumJob {
     // each) and how many
     uint64_t blk_vmask, blk_pos, blk_pp[3];
     int32_t blk_npp;
+    int32_t blk_KB, blk_coefB, blk_ngroups;   // first-product depth / 32, m2 B, unary rows
+    uint64_t blk_grp[3];                      // unary group of each outer monomer (4 bits)
     const int8_t *blk_s2;           // second-product operand of this geometry (8 x 64 x 16 B)
 };
 
@@ -85,7 +87,7 @@ hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t s
 // Persistent batched launch of the blocked form (plain jobs): items of
 // blk_batch_seqs_per_item() sequences (4 blocks), same work-list layout.
 uint64_t blk_batch_seqs_per_item();
-hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, int item_lo, int item_hi,
+hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, int item_lo, int item_hi,
                                  hipStream_t st);
 // Process-wide launch shape of the blocked form (runtime.cpp).
 int blocked_selected_nw();

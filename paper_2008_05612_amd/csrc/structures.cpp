@@ -510,45 +510,131 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
     }
 
     // ---- blocked int8 form ----------------------------------------------------
-    // For a block of sequences sharing every monomer above the low kBlkBits,
-    // F = base + sum_{v low} h_v w_v + sum_{low-low pairs} A C_vv' h_v h_v'
-    // (base: pairs above the low bits; w_v: pairs of v with a monomer above).
-    // Stage one multiplies block-dependent weights into this 0/1 contact
-    // matrix to produce, per conformation, the int8 bytes -m2 base, -m2 w_v,
-    // -m2 A C_vv' and the two window index bytes; stage two multiplies them
-    // with the per-sequence indicators -128 (1, h_v, h_v h_v') and (1, -128),
-    // giving the key 128 m2 F + u.  m2 is the largest power of two with
-    // m2 A nbp <= 128, so every byte stays in range.
+    // For a block of sequences sharing every monomer outside 8 varying ones,
+    // F = base + sum_v h_v w_v + sum_{varying pairs} A C_vv' h_v h_v'
+    // + sum_{outer i} B h_i c_i: base counts the A-weighted contacts between
+    // outer monomers, w_v = A (contacts of v with outer H) + B c_v, and the
+    // unary terms of outer monomers (two-letter tables, B > 0) are split into
+    // groups, one row each.  Stage one multiplies block-dependent weights
+    // into this 0/1 contact matrix to produce, per conformation, the int8
+    // bytes -m2 base, -m2 w_v, -m2 A C_vv', -m2 B (sum of c_i h_i over a
+    // group) and the two window index bytes; stage two multiplies them with
+    // the per-sequence indicators -128 (1, h_v, h_v h_v', 1) and (1, -128),
+    // giving the key 128 m2 F + u.  m2 is the largest power of two keeping
+    // every byte of both block geometries within int8 (bounds taken over all
+    // conformations with every outer monomer H) and the rows within 32.
     s->blk_ok = false;
     s->gemm_b.clear();
-    if (s->U == 0 && N >= kBlkBits && A * int64_t(s->nbp) <= 128 && s->nbp > 0) {
-        int m2 = 1;
-        while (2 * m2 * A * int64_t(s->nbp) <= 128 && m2 < 64)
-            m2 *= 2;
-        int bshift = 7;
-        while ((1 << bshift) < 128 * m2)
-            ++bshift;
-        s->blk_ok = true;
-        s->blk_shift = uint32_t(bshift);
-        s->blk_win_tiles = uint32_t(((1 << bshift) - 1) / kTileConf);
-        s->blk_coef = int32_t(m2 * A);
-        const uint32_t bconf = s->blk_win_tiles * kTileConf;
-        s->gemm_b.assign(s->gemm_a.size(), 0);
-        auto b_byte = [&](uint32_t c, uint32_t k) -> int8_t & {
-            uint32_t t = c / kTileConf, col = c % kTileConf;
-            uint32_t kb = k / 32, kk = k % 32;
-            uint32_t lane = col + 32 * (kk / 16);
-            return s->gemm_b[((size_t(t) * KB + kb) * 64 + lane) * 16 + kk % 16];
-        };
-        for (uint32_t c = 0; c < n_conf; ++c) {
-            for (uint32_t q = 0; q < s->nbp; ++q) {
-                const int i = s->contacts[(size_t(c) * s->nbp + q) * 2];
-                const int j = s->contacts[(size_t(c) * s->nbp + q) * 2 + 1];
-                b_byte(c, pidx[size_t(i) * N + j]) = 1;
+    if (N >= kBlkBits && s->nbp > 0) {
+        // contacts of monomer i in conformation c
+        std::vector<uint8_t> cc(size_t(n_conf) * N, 0);
+        for (uint32_t c = 0; c < n_conf; ++c)
+            for (uint32_t q = 0; q < s->nbp; ++q)
+                for (int e = 0; e < 2; ++e)
+                    ++cc[size_t(c) * N + s->contacts[(size_t(c) * s->nbp + q) * 2 + e]];
+        auto max_sum = [&](const std::vector<int> &mono) {   // max_c sum of c_i over mono
+            int best = 0;
+            for (uint32_t c = 0; c < n_conf; ++c) {
+                int t = 0;
+                for (int i : mono)
+                    t += cc[size_t(c) * N + i];
+                best = std::max(best, t);
             }
-            const uint32_t u = c % bconf + 1;
-            b_byte(c, s->K) = static_cast<int8_t>(u & 127);
-            b_byte(c, s->K + 1) = static_cast<int8_t>(u >> 7);
+            return best;
+        };
+        int maxw[2] = {0, 0};
+        std::vector<int> outer[2];
+        for (int g = 0; g < 2; ++g) {
+            const BlockGeometry geo = block_geometry(N, g == 1);
+            bool vary[64] = {};
+            for (int x = 0; x < 8; ++x)
+                vary[geo.pos[x]] = true;
+            for (int i = 0; i < N; ++i)
+                if (!vary[i])
+                    outer[g].push_back(i);
+            for (int x = 0; x < 8; ++x) {
+                const int v = geo.pos[x];
+                for (uint32_t c = 0; c < n_conf; ++c) {
+                    int with_outer = 0;
+                    for (uint32_t q = 0; q < s->nbp; ++q) {
+                        const int a = s->contacts[(size_t(c) * s->nbp + q) * 2];
+                        const int b = s->contacts[(size_t(c) * s->nbp + q) * 2 + 1];
+                        with_outer += (a == v && !vary[b]) || (b == v && !vary[a]);
+                    }
+                    maxw[g] = std::max(maxw[g], int(A * with_outer + B * cc[size_t(c) * N + v]));
+                }
+            }
+        }
+        int m2 = 64;
+        int ngroups[2] = {0, 0};
+        uint64_t grp[2][3];
+        for (; m2 >= 1; m2 /= 2) {
+            bool fit = int64_t(m2) * A * s->nbp <= 128 && m2 * (A + B) <= 128 &&
+                       2 * m2 * B <= 128 && m2 * std::max(maxw[0], maxw[1]) <= 128;
+            for (int g = 0; g < 2 && fit; ++g) {
+                // unary groups: consecutive outer monomers while m2 B max sum <= 128
+                ngroups[g] = 0;
+                grp[g][0] = grp[g][1] = grp[g][2] = ~uint64_t(0);   // 15: no group
+                if (B > 0) {
+                    std::vector<int> cur;
+                    for (int i : outer[g]) {
+                        cur.push_back(i);
+                        if (int64_t(m2) * B * max_sum(cur) > 128) {
+                            cur.assign(1, i);
+                            ++ngroups[g];
+                            if (int64_t(m2) * B * max_sum(cur) > 128) {
+                                fit = false;
+                                break;
+                            }
+                        }
+                        const int gid = ngroups[g];
+                        grp[g][i / 16] &= ~(uint64_t(15) << (4 * (i % 16)));
+                        grp[g][i / 16] |= uint64_t(gid & 15) << (4 * (i % 16));
+                    }
+                    if (!cur.empty())
+                        ++ngroups[g];
+                }
+                const int npp = block_geometry(N, g == 1).npp;
+                fit = fit && ngroups[g] <= 14 && 9 + npp + ngroups[g] + 2 <= 32;
+            }
+            if (fit)
+                break;
+        }
+        const uint32_t bkb = (s->K + 2 + 31) / 32;
+        const uint32_t kb_cap = B > 0 ? uint32_t(kBlkUnaryMaxKB) : uint32_t(kMaxKB);
+        if (m2 >= 1 && bkb <= kb_cap) {
+            int bshift = 7;
+            while ((1 << bshift) < 128 * m2)
+                ++bshift;
+            s->blk_ok = true;
+            s->blk_KB = bkb;
+            s->blk_shift = uint32_t(bshift);
+            s->blk_win_tiles = uint32_t(((1 << bshift) - 1) / kTileConf);
+            s->blk_coef = int32_t(m2 * A);
+            s->blk_coefB = int32_t(m2 * B);
+            for (int g = 0; g < 2; ++g) {
+                s->blk_ngroups[g] = ngroups[g];
+                for (int w = 0; w < 3; ++w)
+                    s->blk_grp[g][w] = grp[g][w];
+            }
+            const uint32_t bconf = s->blk_win_tiles * kTileConf;
+            s->gemm_b.assign(size_t(n_tiles) * bkb * 1024, 0);
+            auto b_byte = [&](uint32_t c, uint32_t k) -> int8_t & {
+                uint32_t t = c / kTileConf, col = c % kTileConf;
+                uint32_t kb = k / 32, kk = k % 32;
+                uint32_t lane = col + 32 * (kk / 16);
+                return s->gemm_b[((size_t(t) * bkb + kb) * 64 + lane) * 16 + kk % 16];
+            };
+            for (uint32_t c = 0; c < n_conf; ++c) {
+                for (uint32_t q = 0; q < s->nbp; ++q) {
+                    const int i = s->contacts[(size_t(c) * s->nbp + q) * 2];
+                    const int j = s->contacts[(size_t(c) * s->nbp + q) * 2 + 1];
+                    b_byte(c, pidx[size_t(i) * N + j]) = 1;
+                }
+                const uint32_t u = c % bconf + 1;
+                b_byte(c, s->K) = static_cast<int8_t>(u & 127);
+                b_byte(c, s->K + 1) = static_cast<int8_t>(u >> 7);
+            }
         }
     }
 
@@ -558,14 +644,15 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
     // indicator of the virtual row m = 8 (q / 4) + 4 (l / 32) + q % 4 (the
     // row the first product's result register q holds in that lane):
     // m = 0 the block term (-128), 1 .. 8 the weight of varying monomer m-1
-    // (-128 h), then one row per varying pair (-128 h_a h_b), then the two
-    // index bytes (1 and -128).
+    // (-128 h), then one row per varying pair (-128 h_a h_b), one per unary
+    // group (-128), then the two index bytes (1 and -128).
     s->blk_s2.clear();
     if (s->blk_ok) {
         s->blk_s2.assign(2 * 8 * 64 * 16, 0);
         for (int g = 0; g < 2; ++g) {
             const BlockGeometry geo = block_geometry(N, g == 1);
-            const int row_idx = 9 + geo.npp;
+            const int row_un = 9 + geo.npp;
+            const int row_idx = row_un + s->blk_ngroups[g];
             for (int t = 0; t < 8; ++t)
                 for (int lane = 0; lane < 64; ++lane) {
                     const int x = 32 * t + (lane & 31), half = lane >> 5;
@@ -576,8 +663,10 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
                             v = -128;
                         else if (m < 9)
                             v = ((x >> (m - 1)) & 1) ? -128 : 0;
-                        else if (m < row_idx)
+                        else if (m < row_un)
                             v = ((x >> geo.pa[m - 9]) & (x >> geo.pb[m - 9]) & 1) ? -128 : 0;
+                        else if (m < row_idx)
+                            v = -128;
                         else if (m == row_idx)
                             v = 1;
                         else if (m == row_idx + 1)

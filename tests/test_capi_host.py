@@ -143,15 +143,17 @@ def test_argument_errors(lib):
                          None) == -1
     assert lib.hp_sample(s.handle, fake_ws, 9, 5, 0, 16, 1, None, None, None, None, None, None,
                          None) == -1
-    # blocked form: plain ranges of pure pair energies with N >= 8 only
+    # blocked form: plain ranges with N >= 8 and per-block bytes within int8 only
     assert lib.hp_enumerate_symmetric(s.handle, fake_ws, 2, 0, 16, None, None, None, None,
                                       None) == -5
     assert lib.hp_sample(s.handle, fake_ws, 2, 5, 0, 16, 1, None, None, None, None, None, None,
                          None) == -5
     tiny = hp.Structures(2, 3, 1)
     assert lib.hp_enumerate(tiny.handle, fake_ws, 2, 0, 16, None, None, None, None, None) == -5
-    t96 = hp.Structures(4, 4, 1, table=(0, -10, -10, -23))
-    assert lib.hp_enumerate(t96.handle, fake_ws, 2, 0, 16, None, None, None, None, None) == -5
+    # unary weight 25: a monomer with 5 contacts alone fills a byte, so the
+    # unary rows of 3x3x3 exceed the 32 rows of the first product
+    heavy = hp.Structures(3, 3, 3, table=(0, -25, -25, -57))
+    assert lib.hp_enumerate(heavy.handle, fake_ws, 2, 0, 16, None, None, None, None, None) == -5
     assert lib.hp_enumerate(s.handle, fake_ws, 3, 0, 16, None, None, None, None, None) == -1
     assert lib.hp_blocked_select(3, 0) == -1 and lib.hp_blocked_select(4, 3) == -1
     assert lib.hp_autotune_blocked(tiny.handle, fake_ws, 0, 16, 1, None, None, None, None) == -5
@@ -229,7 +231,8 @@ def test_canonical_block_count(lib):
         assert 256 * (2 * (canon - diag) + diag) == 1 << N
     assert hp.hp_canonical_block_count(hp.Structures(3, 3, 3)) == 262656
     assert hp.hp_canonical_block_count(hp.Structures(2, 3, 1)) == 0
-    assert hp.hp_canonical_block_count(hp.Structures(3, 3, 3, table=(0, -10, -10, -23))) == 0
+    assert hp.hp_canonical_block_count(hp.Structures(3, 3, 3, table=(0, -10, -10, -23))) == 262656
+    assert hp.hp_canonical_block_count(hp.Structures(3, 3, 3, table=(0, -25, -25, -57))) == 0
 
 
 def test_low8_pair_list_is_every_odd_pair():
