@@ -6,7 +6,8 @@
 
 Every step of 2^block_bits sequences is one library call; a progress line is
 printed per step.  The default form is the block-factorised int8 form where
-it applies (pure pair energies), else the dense int8 form.  With --symmetric
+it applies (N >= 8; two-letter tables up to a 256-deep first product),
+else the dense int8 form.  With --symmetric
 only reversal-canonical work is scored (about half): canonical sequences
 s <= reverse(s) for the dense and popcount forms (hp_enumerate_symmetric),
 canonical blocks for the blocked form (hp_enumerate_symmetric_blocked); each

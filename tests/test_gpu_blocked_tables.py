@@ -169,7 +169,7 @@ def test_tables_symmetric_blocked_windows(dims):
         assert np.array_equal(out[idx].cpu().numpy().view(np.uint16), ref.out)
 
 
-def test_tables_batch_and_graph():
+def test_tables_batch():
     import torch
     specs = [((4, 4, 1), HP1996, 0, 1 << 16), ((3, 3, 3), HP1996, 5000, 9100),
              ((2, 3, 4), T2, 333, 3333), ((3, 3, 3), None, 100, 2200)]
