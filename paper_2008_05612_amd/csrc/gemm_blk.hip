@@ -1,526 +1,49 @@
-// Block-factorised int8-MFMA form of the ground-state search (pure pair
-// energies).
-//
-// A block is 256 sequences that differ only in 8 "varying" monomers: the low
-// 8 for plain ranges (256 consecutive sequences), the middle 8 for the
-// reversal-canonical blocks (reversal then maps blocks onto blocks).
-// Splitting each pair (i, j) by whether i and j vary, the quantity
-// maximised, F = A sum_k C_k(c) h_i h_j (the negated energy of Eq. 1 up to a
-// constant), becomes
-//   F(s, c) = base(c) + sum_{v varying} h_v w_v(c) + sum_{varying pairs} A C_vv'(c) h_v h_v'
-// with base(c) = A sum over contacts of two outer monomers of h_i h_j and
-// w_v(c) = A sum over contacts of v with an outer monomer j of h_j: numbers
-// that depend on the block and the conformation but not on the varying
-// monomers.  Two products:
-//
-//   stage one  D1 = V x C1, per 32-conformation tile: V holds 32 block-
-//              dependent "virtual rows" (weights -m2 A on outer-outer pairs
-//              for base, -m2 A h_j on the pairs of v for w_v, unit rows
-//              picking the varying pairs and the 2 window index rows) and C1
-//              is the 0/1 contact matrix with the index rows.  D1[m][c] is,
-//              for each conformation, the int8 byte of quantity m: -m2 base,
-//              -m2 w_v, -m2 A C_vv', u & 127 and -(u >> 7).
-//   stage two  key = A2 x S2: A2 = D1 packed to bytes (a lane of the stage-one
-//              result holds one conformation and 16 of its virtual rows,
-//              exactly the 16 bytes it supplies as the A operand of the next
-//              product, so no data moves between lanes), S2 = per-sequence
-//              indicators -128 (1, h_v, h_v h_v') and (1, -128) for the index
-//              bytes, precomputed on the host per block geometry.  The
-//              accumulator is the window key 128 m2 F + u.
-//
-// Per 32 x 32 (conformation x sequence) tile this issues one MFMA of depth
-// 32 instead of K_pad/32 of them; stage one adds K_pad/32 MFMAs per
-// conformation tile per 256 sequences.  The epilogue is the same top-2 key
-// update as the dense form, which now bounds the kernel.
-#include "gemm_body.h"
+// Dispatch of the block-factorised int8 form by product depth.  The kernels
+// themselves (gemm_blk.h) are instantiated per depth in gemm_blk_kb*.hip.
+#include "hp_internal.h"
+#include "kernels.h"
 
 namespace hpmap {
 
+#define HP_BLK_DECLARE(KB)                                                                    \
+    hipError_t launch_gemm_blocked_kb##KB(const EnumJob &j, int nw, int mode, hipStream_t st); \
+    hipError_t launch_gemm_blk_batch_kb##KB(BatchHeader *hdr, int item_lo, unsigned grid,     \
+                                            bool unary, hipStream_t st);
+HP_BLK_DECLARE(1)
+HP_BLK_DECLARE(2)
+HP_BLK_DECLARE(3)
+HP_BLK_DECLARE(4)
+HP_BLK_DECLARE(5)
+HP_BLK_DECLARE(6)
+HP_BLK_DECLARE(7)
+HP_BLK_DECLARE(8)
+HP_BLK_DECLARE(9)
+HP_BLK_DECLARE(10)
+HP_BLK_DECLARE(11)
+HP_BLK_DECLARE(12)
+#undef HP_BLK_DECLARE
+
 namespace {
 
-constexpr int kBlkTiles = (1 << kBlkBits) / 32;   // sequence tiles per block (8)
+using BlockedLaunch = hipError_t (*)(const EnumJob &, int, int, hipStream_t);
+using BlockedBatchLaunch = hipError_t (*)(BatchHeader *, int, unsigned, bool, hipStream_t);
 
-// The 8 varying monomers of a block sit at positions pos(x) (x = 0 .. 7,
-// packed 8 bits each in j.blk_pos); j.blk_vmask has their bits.  Virtual
-// rows: m = 0 base; 1 .. 8 w_v for v = pos(m - 1); then one row per pair of
-// varying monomers with odd separation >= 3 (j.blk_npp pairs, x-indices a | b << 4
-// packed a byte each in j.blk_pp[]); then j.blk_ngroups rows of unary terms
-// (two-letter tables: B c_i h_i summed over a group of outer monomers); then
-// the two index bytes; zero beyond.
-// Plain ranges (CANON false) use the low 8 monomers, a geometry known at
-// compile time: pos(x) = x and the pairs kLow8Pairs, the same list the host
-// lays the second product's operand out by.
-constexpr int kRowW = 1, kRowVV = 9;
-
-template <bool CANON>
-__device__ __forceinline__ int blk_pos(const EnumJob &j, int x)
-{
-    return CANON ? int((j.blk_pos >> (8 * x)) & 0xffu) : x;
-}
-
-template <bool CANON>
-__device__ __forceinline__ int blk_pair(const EnumJob &j, int p)
-{
-    if (!CANON)
-        return p < 8 ? int((kLow8Pairs >> (8 * p)) & 0xffu) : kLow8Pair8;
-    const uint64_t w = p < 8 ? j.blk_pp[0] : (p < 16 ? j.blk_pp[1] : j.blk_pp[2]);
-    return int((w >> (8 * (p & 7))) & 0xffu);
-}
-
-template <bool CANON>
-__device__ __forceinline__ int blk_npp(const EnumJob &j) { return CANON ? j.blk_npp : kLow8NumPairs; }
-
-template <bool CANON>
-__device__ __forceinline__ uint64_t blk_vmask(const EnumJob &j) { return CANON ? j.blk_vmask : 0xffull; }
-
-// Unary group of monomer i (15: none).  Selects, not an indexed read: a
-// runtime index into the job's array would place the job in scratch memory.
-__device__ __forceinline__ int blk_group(const EnumJob &j, int i)
-{
-    const uint64_t w = i < 16 ? j.blk_grp[0] : (i < 32 ? j.blk_grp[1] : j.blk_grp[2]);
-    return int((w >> (4 * (i & 15))) & 15u);
-}
-
-// Stage-one A operand: this lane's virtual row m = lane & 31 over product
-// rows k = 32 kb + 16 half + q of C1, for the block whose outer monomers are
-// the bits of `outer`.
-// UNARY: the job has unary-group rows (two-letter tables); compiled apart so
-// that the pure-pair instances keep this fully unrolled loop small enough to
-// stay in registers at every depth.
-template <int KB, bool CANON, bool UNARY>
-__device__ __forceinline__ void blk_v_fragments(const EnumJob &j, uint64_t outer, int m, int half,
-                                                v4i (&vf)[KB])
-{
-    const int N = j.N;
-    const int coef = j.blk_coef;
-    const int coefB = UNARY ? j.blk_coefB : 0;
-    const uint64_t vmask = blk_vmask<CANON>(j);
-    const int row_un = kRowVV + blk_npp<CANON>(j);
-    const int row_idx = row_un + (UNARY ? j.blk_ngroups : 0);
-    // unary-group rows (two-letter tables): the outer H monomers of this
-    // lane's group, as a bit mask over monomer positions
-    uint64_t gmask = 0;
-    if (UNARY && m >= row_un && m < row_idx)
-        for (int i = 0; i < N; ++i)
-            if (blk_group(j, i) == m - row_un && ((outer >> i) & 1u) && !((vmask >> i) & 1u))
-                gmask |= uint64_t(1) << i;
-    const int wv = m >= kRowW && m < kRowVV ? blk_pos<CANON>(j, m - kRowW) : -1;
-    int va = -1, vb = -1;
-    if (m >= kRowVV && m < row_un) {
-        const int pr = blk_pair<CANON>(j, m - kRowVV);
-        va = blk_pos<CANON>(j, pr & 15);
-        vb = blk_pos<CANON>(j, pr >> 4);
-    }
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-        // product row k < K is the pair (i, i + d) of the k-th odd separation
-        // d >= 3 in (d, i) order: find the first row's pair by skipping whole
-        // runs of length N - d, then advance row by row
-        const int kbase = kb * 32 + half * 16;
-        int d = 3, i = kbase;
-        while (d < N && i >= N - d) {
-            i -= N - d;
-            d += 2;
-        }
-        uint32_t w[4];
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-            uint32_t word = 0;
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) {
-                const int k = kbase + q4 * 4 + bb;
-                int v = 0;
-                if (k == j.K) {
-                    v = m == row_idx ? 1 : 0;
-                } else if (k == j.K + 1) {
-                    v = m == row_idx + 1 ? -1 : 0;
-                } else if (d < N) {
-                    const int jj = i + d;
-                    const bool out_i = !((vmask >> i) & 1u), out_j = !((vmask >> jj) & 1u);
-                    const bool h_i = (outer >> i) & 1u, h_j = (outer >> jj) & 1u;
-                    if (m == 0) {
-                        v = out_i && out_j && h_i && h_j ? -coef : 0;
-                    } else if (m < kRowVV) {
-                        v = (i == wv && out_j && h_j) || (jj == wv && out_i && h_i) ? -coef : 0;
-                        v -= i == wv || jj == wv ? coefB : 0;   // B c_v: every contact of v
-                    } else if (m < row_un) {
-                        v = i == va && jj == vb ? -coef : 0;
-                    } else if (UNARY && m < row_idx) {
-                        v = -coefB * int(((gmask >> i) & 1u) + ((gmask >> jj) & 1u));
-                    }
-                }
-                word |= (uint32_t(v) & 0xffu) << (8 * bb);
-                ++i;   // next row: next i, or the next run
-                if (d < N && i + d >= N) {
-                    i = 0;
-                    d += 2;
-                }
-            }
-            w[q4] = word;
-        }
-        vf[kb] = v4i{int(w[0]), int(w[1]), int(w[2]), int(w[3])};
-    }
-}
-
-// Sequence of block sequence x: the outer bits plus x's bits deposited at the
-// varying positions.
-__device__ __forceinline__ uint64_t blk_sequence(const EnumJob &j, uint64_t outer, int x)
-{
-    uint64_t s = outer;
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-        s |= uint64_t((x >> b) & 1) << blk_pos<true>(j, b);
-    return s;
-}
-
-// Canonical block index t -> outer bits.  With h = j.half_bits outer bits on
-// each side (low: b, high: a) and, for odd N, the middle monomer m as an
-// outer bit, reversal maps the block (a, m, b) onto (rev b, m, rev a); the
-// canonical blocks are a <= b' = rev(b).  The index runs over m, then row
-// pairs p < 2^(h-1) of the (a, b') triangle, each holding row b' = p
-// (a = 0 .. p) and row b' = 2^h - 1 - p (a = 0 .. 2^h - 1 - p).  *diag is
-// set when a == b', i.e. the block is its own reverse.
-// (Block counts stay below 2^28 for N <= 36, so 32-bit arithmetic suffices.)
-__device__ __forceinline__ uint64_t blk_canonical_outer(const EnumJob &j, uint64_t t64, bool *diag)
-{
-    const int h = j.half_bits;
-    const int odd = j.N & 1;
-    const uint32_t t = uint32_t(t64);
-    const uint32_t side = 1u << h;
-    const uint32_t span = side + 1;
-    const uint32_t per_m = h ? (side >> 1) * span : 1;
-    const uint32_t m = t / per_m;
-    const uint32_t r = t - m * per_m;
-    const uint32_t p = h ? r / span : 0;
-    const uint32_t o = r - p * span;
-    const bool first = o <= p;
-    const uint32_t bp = first ? p : side - 1 - p;
-    const uint32_t a = first ? o : o - p - 1;
-    *diag = a == bp;
-    const uint32_t b = h ? (__builtin_bitreverse32(bp) >> (32 - h)) : 0;
-    return (uint64_t(a) << (h + 8 + odd)) | (uint64_t(m) << (h + 4)) | b;
-}
-
-// Low bytes of four int32 values (each in [-128, 127]) packed little-endian,
-// three byte permutes: v_perm_b32(x, y, sel) picks result byte i as byte
-// sel_i of the 8-byte value {x (bytes 4..7), y (bytes 0..3)}; 0x0c gives 0.
-__device__ __forceinline__ int pack4(int a, int b, int c, int d)
-{
-    const uint32_t ab = __builtin_amdgcn_perm(uint32_t(b), uint32_t(a), 0x0c0c0400u);
-    const uint32_t cd = __builtin_amdgcn_perm(uint32_t(d), uint32_t(c), 0x0c0c0400u);
-    return int(__builtin_amdgcn_perm(cd, ab, 0x05040100u));
-}
-
-template <int KB>
-__device__ __forceinline__ v16i stage_one(const v4i (&vf)[KB], const v4i *tile, int lane)
-{
-    v16i d1;
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-        const v16i zero = {};
-        d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(vf[kb], tile[kb * 64 + lane],
-                                                   kb == 0 ? zero : d1, 0, 0, 0);
-    }
-    return d1;
-}
-
-__device__ __forceinline__ v4i pack_d1(const v16i &d1)
-{
-    return v4i{pack4(d1[0], d1[1], d1[2], d1[3]), pack4(d1[4], d1[5], d1[6], d1[7]),
-               pack4(d1[8], d1[9], d1[10], d1[11]), pack4(d1[12], d1[13], d1[14], d1[15])};
-}
-
-// Stage two of one conformation tile for the wave's 8 sequence tiles, with
-// the top-2 key update of each result.  The product of sequence tile t+1 is
-// issued before the key updates of tile t (two accumulators), so the wave
-// does not wait on each product's latency.
-__device__ __forceinline__ void stage_two(const v4i &a2, const v4i (&sf)[kBlkTiles],
-                                          int (&b)[kBlkTiles], int (&sc)[kBlkTiles])
-{
-    const v16i zero = {};
-    v16i acc[2];
-    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[0], zero, 0, 0, 0);
-#pragma unroll
-    for (int t = 0; t < kBlkTiles; ++t) {
-        if (t + 1 < kBlkTiles)
-            acc[(t + 1) & 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[t + 1], zero, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 16; r += 2)
-            top2_add2(b[t], sc[t], acc[t & 1][r], acc[t & 1][r + 1]);
-    }
-}
-
-// Stage two with the per-sequence operand read from LDS just before each
-// product (32 fewer live registers than keeping it in VGPRs).
-__device__ __forceinline__ void stage_two_lds(const v4i &a2, const v4i *s2, int lane,
-                                              int (&b)[kBlkTiles], int (&sc)[kBlkTiles])
-{
-    const v16i zero = {};
-    v16i acc[2];
-    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, s2[lane], zero, 0, 0, 0);
-#pragma unroll
-    for (int t = 0; t < kBlkTiles; ++t) {
-        if (t + 1 < kBlkTiles)
-            acc[(t + 1) & 1] =
-                __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, s2[(t + 1) * 64 + lane], zero, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 16; r += 2)
-            top2_add2(b[t], sc[t], acc[t & 1][r], acc[t & 1][r + 1]);
-    }
-}
-
-// Staging of the C1 tiles:
-//   kBlkLds  : double-buffered LDS, one barrier per tile; stage one of a tile
-//              runs right before its stage two.
-//   kBlkPipe : triple-buffered LDS; the stage-one products of tile t+1 are
-//              issued during iteration t, so the matrix pipe works on them
-//              while the vector ALU runs tile t's key updates.
-//   kBlkLdsS2: as kBlkLds, with the per-sequence operand of stage two held in
-//              LDS (shared by the workgroup) instead of registers.
-enum { kBlkLds = 0, kBlkPipe = 1, kBlkLdsS2 = 2 };
-
-// One wave scores one block of 256 sequences against every conformation
-// tile; the NW waves of a workgroup take consecutive blocks and share the
-// C1 tiles through LDS.
-// The work of one workgroup: wave w scores block blk0 + w (plain jobs: the
-// 256 sequences sharing the bits above the low 8, block index = sequence >> 8;
-// canonical jobs: canonical block index).  lds holds the staged C1 tiles,
-// s2lds the stage-two operand (mode kBlkLdsS2).  Starts and ends at a
-// workgroup barrier, so consecutive calls may reuse the LDS.
-template <int KB, int NW, int MODE, bool CANON, bool UNARY>
-__device__ __forceinline__ void blk_body(const EnumJob &j, uint64_t blk0, v4i *lds, v4i *s2lds)
-{
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int col = lane & 31;
-    const int half = lane >> 5;
-    const uint64_t blk = blk0 + wave;
-    bool diag = false;
-    const uint64_t outer = CANON ? blk_canonical_outer(j, blk, &diag) : blk << kBlkBits;
-    const v4i *__restrict__ B1 = reinterpret_cast<const v4i *>(j.gemm_b);
-
-    v4i vf[KB];
-    blk_v_fragments<KB, CANON, UNARY>(j, outer, col, half, vf);
-    // stage-two B operand: per-sequence indicators, precomputed per geometry
-    v4i sf[MODE == kBlkLdsS2 ? 1 : kBlkTiles];
-    const v4i *__restrict__ S2 = reinterpret_cast<const v4i *>(j.blk_s2);
-    if constexpr (MODE == kBlkLdsS2) {
-        for (int i = threadIdx.x; i < kBlkTiles * 64; i += NW * 64)
-            s2lds[i] = S2[i];   // made visible by the barrier before the tile loop
-    } else {
-#pragma unroll
-        for (int t = 0; t < kBlkTiles; ++t)
-            sf[t] = S2[t * 64 + lane];
-    }
-
-    int b[kBlkTiles], sc[kBlkTiles], gb[kBlkTiles], gs[kBlkTiles];
-#pragma unroll
-    for (int t = 0; t < kBlkTiles; ++t)
-        b[t] = sc[t] = gb[t] = gs[t] = 0;
-
-    const int n_tiles = j.n_tiles;
-    const int win_tiles = j.blk_win_tiles;
-    const int win_shift = j.blk_shift;
-    int wend = min(win_tiles, n_tiles);
-    int conf_base = 0;
-
-    TileStage<KB, NW> stg;
-    constexpr int TV = KB * 64;   // vectors per staged tile
-    if constexpr (MODE == kBlkLds || MODE == kBlkLdsS2) {
-        stg.load(B1, 0);
-        stg.store(lds);
-        __syncthreads();
-        for (int tile = 0; tile < n_tiles; ++tile) {
-            const bool more = tile + 1 < n_tiles;
-            if (more)
-                stg.load(B1, tile + 1);
-            const v16i d1 = stage_one<KB>(vf, lds + (tile & 1) * TV, lane);
-            if constexpr (MODE == kBlkLdsS2)
-                stage_two_lds(pack_d1(d1), s2lds, lane, b, sc);
-            else
-                stage_two(pack_d1(d1), sf, b, sc);
-            if (tile + 1 == wend) {
-                fold_window<kBlkTiles>(b, sc, gb, gs, conf_base, win_shift);
-                conf_base += win_tiles * kTileConf;
-                wend = min(wend + win_tiles, n_tiles);
-            }
-            if (more)
-                stg.store(lds + ((tile + 1) & 1) * TV);
-            __syncthreads();
-        }
-    } else {
-        // Buffer t % 3 holds tile t.  Iteration t: prefetch tile t+2 from
-        // global memory, pack tile t's stage-one result, issue stage one of
-        // tile t+1 (buffer (t+1) % 3) and stage two of tile t, store tile t+2
-        // into buffer (t+2) % 3 = (t-1) % 3 -- last read by stage one of tile
-        // t-1 in iteration t-2, two barriers back -- then one barrier.
-        stg.load(B1, 0);
-        stg.store(lds);
-        if (n_tiles > 1) {
-            stg.load(B1, 1);
-            stg.store(lds + TV);
-        }
-        __syncthreads();
-        v16i d1 = stage_one<KB>(vf, lds, lane);
-        int cur = 0;   // buffer of tile `tile`
-        for (int tile = 0; tile < n_tiles; ++tile) {
-            const bool has1 = tile + 1 < n_tiles;
-            const bool has2 = tile + 2 < n_tiles;
-            if (has2)
-                stg.load(B1, tile + 2);
-            const v4i a2 = pack_d1(d1);
-            const int nxt = cur == 2 ? 0 : cur + 1;
-            const int nn = nxt == 2 ? 0 : nxt + 1;
-            if (has1)
-                d1 = stage_one<KB>(vf, lds + nxt * TV, lane);
-            stage_two(a2, sf, b, sc);
-            if (tile + 1 == wend) {
-                fold_window<kBlkTiles>(b, sc, gb, gs, conf_base, win_shift);
-                conf_base += win_tiles * kTileConf;
-                wend = min(wend + win_tiles, n_tiles);
-            }
-            if (has2)
-                stg.store(lds + nn * TV);
-            __syncthreads();
-            cur = nxt;
-        }
-    }
-
-#pragma unroll
-    for (int t = 0; t < kBlkTiles; ++t) {
-        const int ob = __shfl_xor(gb[t], 32);
-        const int os = __shfl_xor(gs[t], 32);
-        top2_merge(gb[t], gs[t], ob, os);
-        if constexpr (CANON) {
-            // off the diagonal the block's reverse is never scored: write both;
-            // a diagonal block holds each sequence and its reverse itself
-            const uint64_t sq = blk_sequence(j, outer, t * 32 + col);
-            const uint64_t rs = diag ? sq : __builtin_bitreverse64(sq) >> (64 - j.N);
-            finish_sequence(j, sq, sq, rs, half == 0 && blk < j.hi, gb[t], gs[t], lane == 0, 1);
-        } else {
-            const uint64_t idx = outer + uint64_t(t * 32 + col);
-            finish_sequence(j, idx, idx, idx, half == 0 && idx >= j.lo && idx < j.hi, gb[t],
-                            gs[t], lane == 0, 1);
-        }
-    }
-}
-
-template <int KB, int NW, int MODE, bool CANON, bool UNARY>
-__global__ __launch_bounds__(NW * 64) void k_gemm_blk(EnumJob j)
-{
-    __shared__ v4i lds[(MODE == kBlkPipe ? 3 : 2) * KB * 64];
-    __shared__ v4i s2lds[MODE == kBlkLdsS2 ? kBlkTiles * 64 : 1];
-    const uint64_t blk0 = (CANON ? j.lo : j.lo >> kBlkBits) + uint64_t(blockIdx.x) * NW;
-    blk_body<KB, NW, MODE, CANON, UNARY>(j, blk0, lds, s2lds);
-}
-
-// Batched form for jobs of one product depth: workgroup b scores item
-// item_lo + b, NW consecutive blocks of the job whose item range holds it.
-template <int KB, int NW, int MODE, bool UNARY>
-__global__ __launch_bounds__(NW * 64) void k_gemm_blk_batch(BatchHeader *hdr, int item_lo)
-{
-    __shared__ v4i lds[2 * KB * 64];
-    __shared__ v4i s2lds[MODE == kBlkLdsS2 ? kBlkTiles * 64 : 1];
-    const EnumJob *jobs = reinterpret_cast<const EnumJob *>(hdr + 1);
-    const int njobs = hdr->njobs;
-    const int64_t *start = reinterpret_cast<const int64_t *>(jobs + njobs);
-    {
-        // uniform indices let the job be read with scalar loads instead of
-        // occupying vector registers
-        const int it = item_lo + int(blockIdx.x);
-        int lo = 0, hi = njobs - 1;   // job with start[job] <= it < start[job+1]
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) / 2;
-            if (start[mid] <= it)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        lo = __builtin_amdgcn_readfirstlane(lo);
-        const EnumJob &j = jobs[lo];
-        const uint64_t blk0 = (j.lo >> kBlkBits) + uint64_t(it - start[lo]) * NW;
-        blk_body<KB, NW, MODE, false, UNARY>(j, blk0, lds, s2lds);
-    }
-}
-
-template <int KB>
-hipError_t launch_blk_batch_kb(BatchHeader *hdr, int item_lo, unsigned grid, bool unary,
-                               hipStream_t st)
-{
-    constexpr int MODE = KB <= 6 ? kBlkLdsS2 : kBlkLds;
-    if constexpr (KB <= kBlkUnaryMaxKB) {
-        if (unary) {
-            hipLaunchKernelGGL((k_gemm_blk_batch<KB, 4, MODE, true>), dim3(grid), dim3(256), 0,
-                               st, hdr, item_lo);
-            return hipGetLastError();
-        }
-    }
-    if (unary)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_gemm_blk_batch<KB, 4, MODE, false>), dim3(grid), dim3(256), 0, st, hdr,
-                       item_lo);
-    return hipGetLastError();
-}
-
-template <int KB, int NW, int MODE>
-hipError_t launch_blk_shape(const EnumJob &j, hipStream_t st)
-{
-    const bool canon = j.mode == kSeqCanonical;
-    const uint64_t n_blocks =
-        canon ? j.hi - j.lo : ((j.hi - 1) >> kBlkBits) - (j.lo >> kBlkBits) + 1;
-    const dim3 grid(unsigned((n_blocks + NW - 1) / NW));
-    if (canon)
-        hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE, true, false>), grid, dim3(NW * 64), 0, st, j);
-    else
-        hipLaunchKernelGGL((k_gemm_blk<KB, NW, MODE, false, false>), grid, dim3(NW * 64), 0, st, j);
-    return hipGetLastError();
-}
-
-// Two-letter tables: one launch shape (4 waves, staging by depth).
-template <int KB>
-hipError_t launch_blk_unary(const EnumJob &j, hipStream_t st)
-{
-    if constexpr (KB > kBlkUnaryMaxKB) {
-        return hipErrorInvalidValue;
-    } else {
-        constexpr int MODE = KB <= 6 ? kBlkLdsS2 : kBlkLds;
-        const bool canon = j.mode == kSeqCanonical;
-        const uint64_t n_blocks =
-            canon ? j.hi - j.lo : ((j.hi - 1) >> kBlkBits) - (j.lo >> kBlkBits) + 1;
-        const dim3 grid(unsigned((n_blocks + 3) / 4));
-        if (canon)
-            hipLaunchKernelGGL((k_gemm_blk<KB, 4, MODE, true, true>), grid, dim3(256), 0, st, j);
-        else
-            hipLaunchKernelGGL((k_gemm_blk<KB, 4, MODE, false, true>), grid, dim3(256), 0, st, j);
-        return hipGetLastError();
-    }
-}
-
-template <int KB>
-hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
-{
-    if (j.blk_ngroups > 0 || j.blk_coefB != 0)
-        return launch_blk_unary<KB>(j, st);
-    if (mode == kBlkLdsS2) {
-        switch (nw) {
-        case 2: return launch_blk_shape<KB, 2, kBlkLdsS2>(j, st);
-        case 8: return launch_blk_shape<KB, 8, kBlkLdsS2>(j, st);
-        default: return launch_blk_shape<KB, 4, kBlkLdsS2>(j, st);
-        }
-    }
-    if (mode == kBlkPipe) {
-        switch (nw) {
-        case 2: return launch_blk_shape<KB, 2, kBlkPipe>(j, st);
-        case 8: return launch_blk_shape<KB, 8, kBlkPipe>(j, st);
-        default: return launch_blk_shape<KB, 4, kBlkPipe>(j, st);
-        }
-    }
-    switch (nw) {
-    case 2: return launch_blk_shape<KB, 2, kBlkLds>(j, st);
-    case 8: return launch_blk_shape<KB, 8, kBlkLds>(j, st);
-    default: return launch_blk_shape<KB, 4, kBlkLds>(j, st);
-    }
-}
+// Index = product depth / 32 (1 .. kMaxKB).
+const BlockedLaunch kBlocked[] = {
+    nullptr,
+    launch_gemm_blocked_kb1, launch_gemm_blocked_kb2, launch_gemm_blocked_kb3,
+    launch_gemm_blocked_kb4, launch_gemm_blocked_kb5, launch_gemm_blocked_kb6,
+    launch_gemm_blocked_kb7, launch_gemm_blocked_kb8, launch_gemm_blocked_kb9,
+    launch_gemm_blocked_kb10, launch_gemm_blocked_kb11, launch_gemm_blocked_kb12,
+};
+const BlockedBatchLaunch kBlockedBatch[] = {
+    nullptr,
+    launch_gemm_blk_batch_kb1, launch_gemm_blk_batch_kb2, launch_gemm_blk_batch_kb3,
+    launch_gemm_blk_batch_kb4, launch_gemm_blk_batch_kb5, launch_gemm_blk_batch_kb6,
+    launch_gemm_blk_batch_kb7, launch_gemm_blk_batch_kb8, launch_gemm_blk_batch_kb9,
+    launch_gemm_blk_batch_kb10, launch_gemm_blk_batch_kb11, launch_gemm_blk_batch_kb12,
+};
+constexpr int kDepths = int(sizeof(kBlocked) / sizeof(kBlocked[0])) - 1;
 
 }  // namespace
 
@@ -529,23 +52,10 @@ uint64_t blk_batch_seqs_per_item() { return uint64_t(4) << kBlkBits; }
 hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, int item_lo, int item_hi,
                                  hipStream_t st)
 {
-    BatchHeader *hdr = static_cast<BatchHeader *>(d_batch_ws);
-    const unsigned grid = unsigned(item_hi - item_lo);
-    switch (kb) {
-    case 1: return launch_blk_batch_kb<1>(hdr, item_lo, grid, unary, st);
-    case 2: return launch_blk_batch_kb<2>(hdr, item_lo, grid, unary, st);
-    case 3: return launch_blk_batch_kb<3>(hdr, item_lo, grid, unary, st);
-    case 4: return launch_blk_batch_kb<4>(hdr, item_lo, grid, unary, st);
-    case 5: return launch_blk_batch_kb<5>(hdr, item_lo, grid, unary, st);
-    case 6: return launch_blk_batch_kb<6>(hdr, item_lo, grid, unary, st);
-    case 7: return launch_blk_batch_kb<7>(hdr, item_lo, grid, unary, st);
-    case 8: return launch_blk_batch_kb<8>(hdr, item_lo, grid, unary, st);
-    case 9: return launch_blk_batch_kb<9>(hdr, item_lo, grid, unary, st);
-    case 10: return launch_blk_batch_kb<10>(hdr, item_lo, grid, unary, st);
-    case 11: return launch_blk_batch_kb<11>(hdr, item_lo, grid, unary, st);
-    case 12: return launch_blk_batch_kb<12>(hdr, item_lo, grid, unary, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (kb < 1 || kb > kDepths)
+        return hipErrorInvalidValue;
+    return kBlockedBatch[kb](static_cast<BatchHeader *>(d_batch_ws), item_lo,
+                             unsigned(item_hi - item_lo), unary, st);
 }
 
 hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t st)
@@ -554,22 +64,10 @@ hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t s
     // which frees registers for a fourth wave per SIMD (measured faster for
     // K_pad <= 160, slower for 320)
     if (mode < 0)
-        mode = j.blk_KB <= 6 ? kBlkLdsS2 : kBlkLds;
-    switch (j.blk_KB) {
-    case 1: return launch_blk<1>(j, nw, mode, st);
-    case 2: return launch_blk<2>(j, nw, mode, st);
-    case 3: return launch_blk<3>(j, nw, mode, st);
-    case 4: return launch_blk<4>(j, nw, mode, st);
-    case 5: return launch_blk<5>(j, nw, mode, st);
-    case 6: return launch_blk<6>(j, nw, mode, st);
-    case 7: return launch_blk<7>(j, nw, mode, st);
-    case 8: return launch_blk<8>(j, nw, mode, st);
-    case 9: return launch_blk<9>(j, nw, mode, st);
-    case 10: return launch_blk<10>(j, nw, mode, st);
-    case 11: return launch_blk<11>(j, nw, mode, st);
-    case 12: return launch_blk<12>(j, nw, mode, st);
-    default: return hipErrorInvalidValue;
-    }
+        mode = j.blk_KB <= 6 ? kBlkStageS2Lds : kBlkStageLds;
+    if (j.blk_KB < 1 || j.blk_KB > kDepths)
+        return hipErrorInvalidValue;
+    return kBlocked[j.blk_KB](j, nw, mode, st);
 }
 
 }  // namespace hpmap

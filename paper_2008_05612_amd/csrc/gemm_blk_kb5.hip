@@ -1,0 +1,8 @@
+// Blocked int8 form: kernels of product depth(s) K_pad / 32 = 5.
+#include "gemm_blk.h"
+
+namespace hpmap {
+
+HP_BLK_DEPTH(5)
+
+}  // namespace hpmap

@@ -84,6 +84,9 @@ hipError_t launch_popcount(const EnumJob &j, hipStream_t st);
 // buffered LDS with the next tile's first product overlapping this tile's
 // key updates.
 hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t st);
+// Staging modes of the blocked form's contact tiles (gemm_blk.h); mode < 0
+// picks by product depth.
+enum BlkStage { kBlkStageLds = 0, kBlkStagePipe = 1, kBlkStageS2Lds = 2 };
 // Persistent batched launch of the blocked form (plain jobs): items of
 // blk_batch_seqs_per_item() sequences (4 blocks), same work-list layout.
 uint64_t blk_batch_seqs_per_item();
