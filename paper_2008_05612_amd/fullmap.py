@@ -69,9 +69,11 @@ def _save_checkpoint(path, dims, form, block_bits, symmetric, table, next_block,
 
 def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
         checkpoint=None, progress=print, device="cuda", symmetric=False, table=None,
-        phi=False):
+        phi=False, fill=None):
     """Enumerate all 2^N sequences of the box; returns a summary dict (and the
-    device map under key "map" when keep_map)."""
+    device map under key "map" when keep_map).  With `fill` (an int16 value
+    that is no phenotype) the map starts filled with it and the summary
+    counts the entries still holding it at the end ("unwritten")."""
     import numpy as np
     import torch
 
@@ -105,6 +107,8 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
                              "--neighbors / --phi")
         progress("resuming at block %d of %d" % (start_block, n_blocks))
     out = torch.empty(total, dtype=torch.int16, device=device) if keep_map else None
+    if out is not None and fill is not None:
+        out.fill_(fill)
     t0 = time.time()
     for b in range(start_block, n_blocks):
         lo, hi = b * block, min((b + 1) * block, space)
@@ -140,6 +144,8 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
         "designability_sha256": hashlib.sha256(d.astype("<u8").tobytes()).hexdigest(),
         "sum_check": int(d.sum()) + nd == total,
     }
+    if out is not None and fill is not None:
+        summary["unwritten"] = int((out == fill).sum().item())
     if neighbors and out is not None:
         z = lambda n: torch.zeros(n, dtype=torch.int64, device=device)  # noqa: E731
         neu, dele, oth, row = z(s.n_class), z(s.n_class), z(s.n_class), z(s.n_class + 1)

@@ -1,14 +1,14 @@
 """Full-map driver: checkpoint/resume, and the full 6x6 map.
 
 The 6x6 map (2^36 sequences x 57337 conformations, 137 GB resident; the
-blocked form over reversal-canonical blocks) takes a few minutes, so it only
-runs when HP_RUN_FULLMAP=1.  Its parity checks:
-the sum and symmetry invariants over all 2^36 sequences (symmetry on a large
-random sample), oracle windows at both ends and at seeded offsets, and the
-popcount form on sampled windows.
+blocked form over reversal-canonical blocks, in steps of 2^25 blocks, so that
+every step crosses the library's own cuts at 2^22 blocks).  Its parity
+checks: every entry written and the sum invariant over all 2^36 sequences,
+the symmetry invariant on a large random sample, oracle windows at both ends
+and at seeded offsets, the oracle on the blocks on both sides of launch
+cuts, and the popcount form on sampled windows.
 """
 import json
-import os
 
 import numpy as np
 import pytest
@@ -16,6 +16,7 @@ import pytest
 import oracle
 import paper_2008_05612_amd as hp
 from paper_2008_05612_amd import fullmap
+from tests._canon import canonical_block_sequences, reverse_bits
 from tests.conftest import gpu_available
 
 pytestmark = pytest.mark.gpu
@@ -78,11 +79,9 @@ def test_checkpoint_resume_symmetric(tmp_path, form):
     assert res["nondesign"] == ref["nondesign"]
 
 
-@pytest.mark.skipif(os.environ.get("HP_RUN_FULLMAP") != "1",
-                    reason="full 6x6 map takes minutes; set HP_RUN_FULLMAP=1")
 def test_full_6x6_map():
     import torch
-    res = fullmap.run((6, 6, 1), neighbors=True, symmetric=True,
+    res = fullmap.run((6, 6, 1), neighbors=True, symmetric=True, block_bits=33, fill=-2,
                       progress=lambda m: print(m, flush=True))
     pub = {k: v for k, v in res.items() if not k.startswith("_") and k != "map"}
     print(json.dumps(pub), flush=True)
@@ -91,6 +90,7 @@ def test_full_6x6_map():
     N = 36
     d = res["_designability"]
     assert res["sum_check"] and res["neighbor_sum_check"]
+    assert res["unwritten"] == 0
     assert np.all(d[s.export()["self_rev"] == 0] % 2 == 0)
     neu = res["_counts"][0]
     assert np.all(neu % 2 == 0)
@@ -108,6 +108,14 @@ def test_full_6x6_map():
     for lo in offs:
         gs = oracle.ground_states(st, lo, lo + 4096)
         assert np.array_equal(out[lo:lo + 4096].cpu().numpy().view(np.uint16), gs.out), lo
+    # the blocks on both sides of launch cuts (2^22 canonical blocks per launch)
+    for t in (1 << 22) - 1, 1 << 22, (5 << 22) - 1, 5 << 22:
+        seqs, diag = canonical_block_sequences(N, t)
+        gs = oracle.ground_states_gap(st, seqs, threshold=1)
+        idx = torch.from_numpy(seqs.view(np.int64)).cuda()
+        ridx = torch.from_numpy(reverse_bits(seqs, N).view(np.int64)).cuda()
+        assert np.array_equal(out[idx].cpu().numpy().view(np.uint16), gs.out), t
+        assert np.array_equal(out[ridx].cpu().numpy().view(np.uint16), gs.out), t
     # popcount form on sampled windows of the resident map
     for lo in offs[:3]:
         o2 = torch.empty(1 << 20, dtype=torch.int16, device="cuda")
