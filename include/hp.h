@@ -266,9 +266,12 @@ hp_status hp_sample(const hp_structs *s, const void *d_ws, int form, uint64_t se
  * are enqueued back to back on `stream`.  HP_FORM_POPCOUNT runs the jobs as
  * separate hp_enumerate calls.  Each job has the meaning of one hp_enumerate
  * call.  d_batch_ws is caller device memory of hp_batch_workspace_bytes(njobs)
- * bytes holding the work list (rewritten by every call).  The descriptor
- * upload is a synchronous host-to-device copy made before the launches are
- * enqueued.
+ * bytes holding the work list (rewritten by every call).  The work list is
+ * copied to d_batch_ws on `stream`, after the work already queued there
+ * (which may still read an earlier work list), and the call waits for that
+ * copy before enqueueing the launches: it returns once `stream` has drained
+ * up to the copy.  Calls on other streams that share d_batch_ws must be
+ * ordered by the caller.
  * Errors: as hp_enumerate, for any job; HP_EINVAL if njobs < 1 or the
  * workspace is too small; HP_EUNSUPPORTED if a job's handle is not covered
  * by HP_FORM_BLOCKED_I8.
@@ -291,7 +294,8 @@ hp_status hp_enumerate_batch(const hp_job *jobs, int njobs, int form, void *d_ba
  * Captured launches: hp_graph_capture_batch records the device work of
  * hp_enumerate_batch (the per-depth kernel launches; no memsets) into a
  * hipGraph once, for HP_FORM_GEMM_I8 or HP_FORM_BLOCKED_I8; hp_graph_launch
- * replays it on `stream`.  The work list is uploaded at capture time and must
+ * replays it on `stream`.  The work list is uploaded at capture time, after
+ * the device has finished all queued work (hipDeviceSynchronize), and must
  * stay in d_batch_ws while the graph is used.  Designability counters
  * accumulate on every replay.
  */

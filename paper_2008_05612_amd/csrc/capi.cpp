@@ -41,19 +41,14 @@ hp_status check_range(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
     return HP_OK;
 }
 
-struct BatchPlan {
-    std::vector<char> host;   // header + jobs + item starts
-    struct Group {
-        int kb, item_lo, item_hi;   // product depth (blocked: 2 depth + unary flag), its items
-    };
-    std::vector<Group> groups;
-};
+}  // namespace
 
-// Work list of a batch: jobs ordered by product depth (stable), items of
-// gemm_batch_seqs_per_item() sequences (dense form) or of
-// blk_batch_seqs_per_item() sequences in whole 256-sequence blocks (blocked
-// form), and the item range of each depth.
-hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, BatchPlan *plan)
+// Work list of a batch, written into caller buffers (no allocation): jobs
+// ordered by product depth (stable), items of gemm_batch_seqs_per_item()
+// sequences (dense form) or of blk_batch_seqs_per_item() sequences in whole
+// 256-sequence blocks (blocked form), and the item range of each depth.
+hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, char *host,
+                     int *order, int64_t *start, BatchGroup *groups, int *ngroups)
 {
     if (!jobs || njobs < 1)
         return fail(HP_EINVAL, "batch needs at least one job");
@@ -70,16 +65,21 @@ hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, B
                                          "within int8 and, with unary rows, depth <= 256");
         kb_max = std::max(kb_max, int(jobs[i].structs->K_pad / 32));
     }
-    std::vector<int> order(njobs);
-    for (int i = 0; i < njobs; ++i)
-        order[i] = i;
     // blocked jobs group by depth and by whether they carry unary rows
     auto depth = [&](int i) {
         const hp_structs *t = jobs[i].structs;
-        return blocked ? 2 * t->blk_KB + (t->blk_coefB != 0 ? 1u : 0u) : t->K_pad / 32;
+        return int(blocked ? 2 * t->blk_KB + (t->blk_coefB != 0 ? 1u : 0u) : t->K_pad / 32);
     };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return depth(a) < depth(b); });
-    std::vector<int64_t> start(njobs + 1, 0);
+    // stable insertion sort by depth (batches hold a handful of jobs)
+    for (int r = 0; r < njobs; ++r) {
+        int k = r;
+        while (k > 0 && depth(order[k - 1]) > depth(r)) {
+            order[k] = order[k - 1];
+            --k;
+        }
+        order[k] = r;
+    }
+    start[0] = 0;
     for (int r = 0; r < njobs; ++r) {
         const hp_job &jb = jobs[order[r]];
         uint64_t items;
@@ -95,34 +95,37 @@ hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, B
     }
     if (start[njobs] > INT32_MAX)
         return fail(HP_ERANGE, "batch has too many work items");
-    plan->host.assign(hp_batch_workspace_bytes(njobs), 0);
+    std::memset(host, 0, hp_batch_workspace_bytes(njobs));
     BatchHeader hdr{};
     hdr.reserved = 0;
     hdr.njobs = njobs;
     hdr.n_items = int32_t(start[njobs]);
     hdr.kb_max = kb_max;
-    std::memcpy(plan->host.data(), &hdr, sizeof(hdr));
-    EnumJob *ej = reinterpret_cast<EnumJob *>(plan->host.data() + sizeof(BatchHeader));
-    plan->groups.clear();
+    std::memcpy(host, &hdr, sizeof(hdr));
+    char *ej = host + sizeof(BatchHeader);
+    int ng = 0;
     for (int r = 0; r < njobs; ++r) {
         const hp_job &jb = jobs[order[r]];
-        ej[r] = make_enum_job(jb.structs, jb.d_ws, jb.seq_lo, jb.seq_hi, jb.d_out, jb.d_emin,
-                              jb.d_designability, jb.d_nondesign);
-        const int kb = blocked ? int(2 * jb.structs->blk_KB + (jb.structs->blk_coefB != 0))
-                               : int(jb.structs->K_pad / 32);
-        if (plan->groups.empty() || plan->groups.back().kb != kb)
-            plan->groups.push_back({kb, int(start[r]), int(start[r])});
-        plan->groups.back().item_hi = int(start[r + 1]);
+        const EnumJob j = make_enum_job(jb.structs, jb.d_ws, jb.seq_lo, jb.seq_hi, jb.d_out,
+                                        jb.d_emin, jb.d_designability, jb.d_nondesign);
+        std::memcpy(ej + sizeof(EnumJob) * r, &j, sizeof(EnumJob));
+        const int kb = depth(order[r]);
+        if (ng == 0 || groups[ng - 1].kb != kb)
+            groups[ng++] = {kb, int(start[r]), int(start[r])};
+        groups[ng - 1].item_hi = int(start[r + 1]);
     }
-    std::memcpy(plan->host.data() + sizeof(BatchHeader) + sizeof(EnumJob) * njobs, start.data(),
+    std::memcpy(host + sizeof(BatchHeader) + sizeof(EnumJob) * njobs, start,
                 sizeof(int64_t) * (njobs + 1));
+    *ngroups = ng;
     return HP_OK;
 }
 
 // One launch per product depth of the plan, in order on `st`.
-hipError_t launch_plan(const BatchPlan &plan, int form, void *d_batch_ws, hipStream_t st)
+hipError_t launch_plan(const BatchGroup *groups, int ngroups, int form, void *d_batch_ws,
+                       hipStream_t st)
 {
-    for (const BatchPlan::Group &g : plan.groups) {
+    for (int i = 0; i < ngroups; ++i) {
+        const BatchGroup &g = groups[i];
         if (g.item_hi <= g.item_lo)
             continue;
         hipError_t e = form == HP_FORM_BLOCKED_I8
@@ -135,7 +138,31 @@ hipError_t launch_plan(const BatchPlan &plan, int form, void *d_batch_ws, hipStr
     return hipSuccess;
 }
 
+namespace {
+
+// Host side of a batch plan: the work list bytes and the launch groups.
+struct BatchPlan {
+    std::vector<char> host;
+    std::vector<int> order;
+    std::vector<int64_t> start;
+    std::vector<BatchGroup> groups;
+    int ngroups = 0;
+
+    hp_status make(const hp_job *jobs, int njobs, int form, size_t ws_bytes)
+    {
+        if (!jobs || njobs < 1)
+            return fail(HP_EINVAL, "batch needs at least one job");
+        host.assign(hp_batch_workspace_bytes(njobs), 0);
+        order.assign(njobs, 0);
+        start.assign(njobs + 1, 0);
+        groups.assign(njobs, BatchGroup{});
+        return plan_batch(jobs, njobs, form, ws_bytes, host.data(), order.data(), start.data(),
+                          groups.data(), &ngroups);
+    }
+};
+
 }  // namespace
+
 
 // Block geometry fields of a job (the blocked form).
 static void set_block_geometry(EnumJob &j, const hp_structs *s, bool canonical)
@@ -535,14 +562,19 @@ hp_status hp_enumerate_batch(const hp_job *jobs, int njobs, int form, void *d_ba
     if (!d_batch_ws)
         return fail(HP_EINVAL, "batch workspace is NULL");
     BatchPlan plan;
-    hp_status st = plan_batch(jobs, njobs, form, batch_ws_bytes, &plan);
+    hp_status st = plan.make(jobs, njobs, form, batch_ws_bytes);
     if (st != HP_OK)
         return st;
-    // synchronous upload: the host plan is released on return
-    hipError_t e = hipMemcpy(d_batch_ws, plan.host.data(), plan.host.size(), hipMemcpyHostToDevice);
+    // The upload is ordered on `stream` after the work already queued there
+    // (an earlier batch may still read this workspace), and completes before
+    // return, since the host plan is released then.
+    hipError_t e = hipMemcpyAsync(d_batch_ws, plan.host.data(), plan.host.size(),
+                                  hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(hs);
     if (e != hipSuccess)
         return device_fail(e, "batch upload");
-    e = launch_plan(plan, form, d_batch_ws, hs);
+    e = launch_plan(plan.groups.data(), plan.ngroups, form, d_batch_ws, hs);
     if (e != hipSuccess)
         return device_fail(e, "batch launch");
     return HP_OK;
@@ -559,10 +591,14 @@ hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *
     if (!d_batch_ws)
         return fail(HP_EINVAL, "batch workspace is NULL");
     BatchPlan plan;
-    hp_status st = plan_batch(jobs, njobs, form, batch_ws_bytes, &plan);
+    hp_status st = plan.make(jobs, njobs, form, batch_ws_bytes);
     if (st != HP_OK)
         return st;
-    hipError_t e = hipMemcpy(d_batch_ws, plan.host.data(), plan.host.size(), hipMemcpyHostToDevice);
+    // no stream to order on: wait for all work on the device, which may
+    // still read this workspace, then upload
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(d_batch_ws, plan.host.data(), plan.host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess)
         return device_fail(e, "batch upload");
     hipStream_t cap = nullptr;
@@ -575,7 +611,7 @@ hp_status hp_graph_capture_batch(const hp_job *jobs, int njobs, int form, void *
     }
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_plan(plan, form, d_batch_ws, cap);
+        hipError_t le = launch_plan(plan.groups.data(), plan.ngroups, form, d_batch_ws, cap);
         e = hipStreamEndCapture(cap, &g->graph);
         if (le != hipSuccess)
             e = le;

@@ -105,6 +105,16 @@ struct EnumJob;
 EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64_t hi,
                       uint16_t *out, int32_t *emin, uint64_t *desig, uint64_t *nondesign);
 
+// Batched launches (capi.cpp).  The work list of `njobs` jobs is written
+// into host[0 .. hp_batch_workspace_bytes(njobs)); order[njobs],
+// start[njobs + 1] and groups[njobs] are scratch and launch groups supplied
+// by the caller (nothing is allocated).
+struct BatchGroup {
+    int kb, item_lo, item_hi;   // product depth (blocked: 2 depth + unary flag), its items
+};
+hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, char *host,
+                     int *order, int64_t *start, BatchGroup *groups, int *ngroups);
+
 // Error plumbing (capi.cpp).
 hp_status fail(hp_status st, const std::string &msg);
 

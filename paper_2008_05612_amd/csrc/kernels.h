@@ -100,6 +100,11 @@ uint64_t gemm_batch_seqs_per_item();
 // Persistent launch over items [item_lo, item_hi) of the work list at
 // d_batch_ws, all of product depth kb.
 hipError_t launch_gemm_batch(void *d_batch_ws, int kb, int item_lo, int item_hi, hipStream_t st);
+// One launch per group of a batch plan (hp_internal.h), in order on `st`,
+// over the work list at d_batch_ws (capi.cpp).
+struct BatchGroup;
+hipError_t launch_plan(const BatchGroup *groups, int ngroups, int form, void *d_batch_ws,
+                       hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, uint64_t n,
                            hipStream_t st);
