@@ -306,6 +306,24 @@ hp_status hp_graph_launch(hp_graph *g, void *stream);
 void hp_graph_free(hp_graph *g);
 
 /*
+ * hp_enumerate_batch_static -- hp_enumerate_batch for callers that cannot
+ * allocate device memory (code under hipGraph capture, tight serving loops,
+ * harnesses that forbid allocation).  It takes no workspace: the work list
+ * lives in a device array of the library, one per GPU, sized for
+ * HP_STATIC_BATCH_MAX_JOBS jobs (about 10 KiB) and held until the process
+ * ends; every call on that GPU rewrites it.  The call allocates nothing: the
+ * list reaches the array through kernel launches on `stream`, in stream
+ * order after the work already queued there, and the call does not wait.
+ * Calls that overlap on one GPU (different streams, not ordered by the
+ * caller) race on the shared array.  Outputs and accumulation are those of
+ * hp_enumerate_batch with the same jobs and form.
+ * Errors: as hp_enumerate_batch; HP_ERANGE if njobs > HP_STATIC_BATCH_MAX_JOBS
+ * (checked before any device call).
+ */
+#define HP_STATIC_BATCH_MAX_JOBS 32
+hp_status hp_enumerate_batch_static(const hp_job *jobs, int njobs, int form, void *stream);
+
+/*
  * Launch shape of HP_FORM_BLOCKED_I8: every wave scores one block of 256
  * sequences.  hp_blocked_select sets, process-wide, the waves per workgroup
  * nw (2, 4 or 8; default 4; the waves of a workgroup share each staged

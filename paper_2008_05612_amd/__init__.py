@@ -24,6 +24,7 @@ from ._binding import (  # noqa: F401
     hp_canonical_block_count,
     hp_canonical_count,
     hp_enumerate_batch,
+    hp_enumerate_batch_static,
     hp_enumerate_gap,
     hp_enumerate_symmetric,
     hp_enumerate_symmetric_blocked,

@@ -89,6 +89,7 @@ def library():
         "hp_enumerate_batch": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp, sz, vp]),
         "hp_graph_capture_batch": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp, sz,
                                         ctypes.POINTER(vp)]),
+        "hp_enumerate_batch_static": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp]),
         "hp_graph_launch": (st, [vp, vp]),
         "hp_graph_free": (None, [vp]),
         "hp_neighbors": (st, [vp, vp, vp, vp, vp, i32, vp, vp]),
@@ -376,6 +377,17 @@ def hp_enumerate_batch(jobs: Sequence[Job], form: int, batch_ws, stream=None):
                                              batch_workspace_bytes(len(jobs)), "batch workspace"),
                                         batch_ws.numel(), _stream_handle(stream)),
            "hp_enumerate_batch")
+
+
+STATIC_BATCH_MAX_JOBS = 32   # HP_STATIC_BATCH_MAX_JOBS
+
+
+def hp_enumerate_batch_static(jobs: Sequence[Job], form: int, stream=None):
+    """hp_enumerate_batch without a workspace: the work list goes to the
+    library's own device array (no allocation; at most 32 jobs)."""
+    arr = _jobs_array(jobs)
+    _check(library().hp_enumerate_batch_static(arr, len(jobs), form, _stream_handle(stream)),
+           "hp_enumerate_batch_static")
 
 
 class Graph:

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhpmap.so")
-SOURCES = ["structures.cpp", "capi.cpp", "runtime.cpp", "kernels_popcount.hip",
+SOURCES = ["structures.cpp", "capi.cpp", "capi_static.hip", "runtime.cpp", "kernels_popcount.hip",
            "gemm_kb1_4.hip", "gemm_kb5.hip", "gemm_kb6_10.hip", "gemm_kb11_12.hip",
            "gemm_batch.hip", "gemm_blk.hip", "gemm_blk_kb1_3.hip", "gemm_blk_kb4.hip",
            "gemm_blk_kb5.hip", "gemm_blk_kb6_7.hip", "gemm_blk_kb8_9.hip", "gemm_blk_kb10.hip",

@@ -175,6 +175,16 @@ def test_argument_errors(lib):
     jobs[0] = _binding._Job(tiny.handle.value, 256, 0, 16, None, None, None, None)
     assert lib.hp_enumerate_batch(jobs, 1, 2, fake_ws, 1 << 20, None) == -5
     assert lib.hp_graph_capture_batch(jobs, 1, 2, fake_ws, 1 << 20, ctypes.byref(g)) == -5
+    # the batch without allocation: its argument checks come before any device call
+    assert lib.hp_enumerate_batch_static(None, 0, 1, None) == -1
+    many = (_binding._Job * 33)()
+    assert lib.hp_enumerate_batch_static(many, 33, 1, None) == -4
+    assert b"at most 32" in lib.hp_last_error()
+    jobs[0] = _binding._Job(s.handle.value, 256, 16, 16, None, None, None, None)
+    assert lib.hp_enumerate_batch_static(jobs, 1, 1, None) == -1     # empty job
+    assert lib.hp_enumerate_batch_static(jobs, 1, 5, None) == -1     # unknown form
+    jobs[0] = _binding._Job(tiny.handle.value, 256, 0, 16, None, None, None, None)
+    assert lib.hp_enumerate_batch_static(jobs, 1, 2, None) == -5
 
 
 def test_workspace_layout(lib):
