@@ -218,6 +218,40 @@ hp_status hp_enumerate_symmetric_blocked(const hp_structs *s, const void *d_ws, 
                                          void *stream);
 
 /*
+ * Reversal symmetry with wide blocks of HP_FORM_BLOCKED_I8 (pure pair
+ * energies, N >= 10; hp_wide_block_count is 0 when a handle is not covered).
+ * A wide block is 1024 sequences that differ only in the 10 monomers around
+ * the middle: positions h .. h+9 for even N; for odd N positions h .. h+4
+ * and h+6 .. h+10, the middle monomer h+5 staying outer; h = (N - 10 - N % 2)
+ * / 2.  Reversal maps wide blocks onto wide blocks; with a = the h highest
+ * monomers (and m the middle one for odd N), b = the h lowest and b' =
+ * reverse(b), the canonical wide blocks are those with a <= b'.  One
+ * workgroup of 4 waves scores a wide block, the first product of each
+ * conformation tile computed once for all four waves.
+ *   hp_wide_block_count  number of canonical wide blocks: about 2^N / 2048.
+ *   hp_enumerate_symmetric_wide  scores canonical wide blocks [b_lo, b_hi)
+ *                        and fills d_out / d_emin (full 2^N-entry maps,
+ *                        indexed by sequence) at every sequence s of the
+ *                        block and, for blocks with a < b', at reverse(s);
+ *                        designability and the deleterious count add 2 per
+ *                        such s and 1 for the sequences of blocks with
+ *                        a == b'.  Over [0, hp_wide_block_count) the outputs
+ *                        equal those of hp_enumerate over [0, 2^N).  Ranges
+ *                        longer than 2^20 blocks run as several launches.
+ * Block index order: as for hp_enumerate_symmetric_blocked (over m, then row
+ * pairs p < 2^(h-1) of the (a, b') triangle, row b' = p then row
+ * b' = 2^h - 1 - p).
+ * Errors: HP_EINVAL for a NULL handle or workspace, an empty range or
+ * b_hi > hp_wide_block_count; HP_EUNSUPPORTED for a handle wide blocks do not
+ * cover; HP_EDEVICE for a failed launch.
+ */
+uint64_t hp_wide_block_count(const hp_structs *s);
+hp_status hp_enumerate_symmetric_wide(const hp_structs *s, const void *d_ws, uint64_t b_lo,
+                                      uint64_t b_hi, uint16_t *d_out, int32_t *d_emin,
+                                      uint64_t *d_designability, uint64_t *d_nondesign,
+                                      void *stream);
+
+/*
  * Energy gap and threshold (Methods, end of "HP and MJ lattice models": the
  * threshold is the smallest difference between the lowest and second-lowest
  * fold energies that counts as distinguishable; closer than that, the
@@ -260,9 +294,11 @@ hp_status hp_sample(const hp_structs *s, const void *d_ws, int form, uint64_t se
 /*
  * Batched launch: several enumeration jobs, possibly of different lattices
  * and uneven sizes, from one work list of fixed-size items (256 sequences
- * for HP_FORM_GEMM_I8, 4 blocks of 256 for HP_FORM_BLOCKED_I8).  Jobs are
- * grouped by product depth (hp_info.K_pad) and each group is one kernel
- * launch, compiled for that depth, with one workgroup per item; the groups
+ * for HP_FORM_GEMM_I8; for HP_FORM_BLOCKED_I8 one wide block of 1024 where
+ * wide blocks apply and the selected staging mode is -1 or 3, else 4 blocks
+ * of 256).  Jobs are grouped by product depth (hp_info.K_pad; blocked: also
+ * by wide blocks and unary rows) and each group is one kernel launch,
+ * compiled for that depth, with one workgroup per item; the groups
  * are enqueued back to back on `stream`.  HP_FORM_POPCOUNT runs the jobs as
  * separate hp_enumerate calls.  Each job has the meaning of one hp_enumerate
  * call.  d_batch_ws is caller device memory of hp_batch_workspace_bytes(njobs)
@@ -331,19 +367,25 @@ hp_status hp_enumerate_batch_static(const hp_job *jobs, int njobs, int form, voi
  * triple-buffered LDS with the block-level product of the next tile issued
  * while the current tile's keys are updated; 2: as 0, with the per-sequence
  * operand of the second product read from LDS instead of held in registers;
- * -1, default: 2 for K_pad <= 192, else 0).  hp_blocked_selected reports
- * them (either pointer may be NULL).  Results never depend on the shape.
- * Errors: HP_EINVAL for another value.
+ * 3: wide blocks, 1024 sequences sharing every monomer above the low 10 per
+ * workgroup of 4 waves, one first product per conformation tile shared by
+ * the waves -- pure pair energies over plain ranges only, elsewhere mode 3
+ * acts as -1; -1, default: 3 where wide blocks apply, else 2 for
+ * K_pad <= 192, else 0).  hp_blocked_selected
+ * reports them (either pointer may be NULL).  Results never depend on the
+ * shape.
+ * Errors: HP_EINVAL for another value, or mode 3 with nw != 4.
  */
 hp_status hp_blocked_select(int nw, int mode);
 void hp_blocked_selected(int *nw, int *mode);
 /*
- * hp_autotune_blocked -- time the 9 launch shapes of HP_FORM_BLOCKED_I8
- * (nw = 2, 4, 8 x mode = 0, 1, 2; entry i is nw = {2,4,8}[i / 3], mode =
- * i % 3) on sequences [seq_lo, seq_lo + n_seq) (no outputs written, `repeats`
- * launches each after one warm-up), select the fastest process-wide, and
- * report per-shape milliseconds in ms[9] and the choice (any pointer may be
- * NULL).  Synchronises `stream`.
+ * hp_autotune_blocked -- time the launch shapes of HP_FORM_BLOCKED_I8
+ * (entries 0 .. 8: nw = 2, 4, 8 x mode = 0, 1, 2, entry i is nw =
+ * {2,4,8}[i / 3], mode = i % 3; entry 9: wide blocks, nw 4, mode 3, where
+ * they apply, else ms[9] = -1) on sequences [seq_lo, seq_lo + n_seq) (no
+ * outputs written, `repeats` launches each after one warm-up), select the
+ * fastest process-wide, and report per-shape milliseconds in ms[10] and the
+ * choice (any pointer may be NULL).  Synchronises `stream`.
  * Errors: HP_EUNSUPPORTED for a handle the blocked form does not cover;
  * HP_EINVAL for a range outside [0, 2^N); HP_EDEVICE for a failed launch.
  */

@@ -28,6 +28,7 @@ from ._binding import (  # noqa: F401
     hp_enumerate_gap,
     hp_enumerate_symmetric,
     hp_enumerate_symmetric_blocked,
+    hp_enumerate_symmetric_wide,
     hp_gemm_select,
     hp_gemm_selected,
     hp_gemm_shapes,
@@ -38,6 +39,7 @@ from ._binding import (  # noqa: F401
     hp_sample,
     hp_structures,
     hp_upload,
+    hp_wide_block_count,
     hp_workspace_bytes,
     library,
     library_path,

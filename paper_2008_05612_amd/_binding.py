@@ -84,6 +84,8 @@ def library():
         "hp_enumerate_symmetric": (st, [vp, vp, ctypes.c_int, u64, u64, vp, vp, vp, vp, vp]),
         "hp_canonical_block_count": (u64, [vp]),
         "hp_enumerate_symmetric_blocked": (st, [vp, vp, u64, u64, vp, vp, vp, vp, vp]),
+        "hp_wide_block_count": (u64, [vp]),
+        "hp_enumerate_symmetric_wide": (st, [vp, vp, u64, u64, vp, vp, vp, vp, vp]),
         "hp_enumerate_gap": (st, [vp, vp, ctypes.c_int, u64, u64, i32, vp, vp, vp, vp, vp, vp]),
         "hp_sample": (st, [vp, vp, ctypes.c_int, u64, u64, u64, i32, vp, vp, vp, vp, vp, vp, vp]),
         "hp_enumerate_batch": (st, [ctypes.POINTER(_Job), ctypes.c_int, ctypes.c_int, vp, sz, vp]),
@@ -250,10 +252,11 @@ def hp_enumerate(s: Structures, ws, form: int, seq_lo: int, seq_hi: int, out=Non
 
 def hp_autotune_blocked(s: Structures, ws, seq_lo: int = 0, n_seq: int = 1 << 20,
                         repeats: int = 2, stream=None):
-    """Time the 9 blocked-form launch shapes, select the fastest; returns
-    ((nw, mode), [ms per shape in hp.h order])."""
+    """Time the blocked-form launch shapes (9, plus wide blocks where they
+    apply), select the fastest; returns ((nw, mode), [ms per shape in hp.h
+    order; -1 for a shape that does not apply])."""
     import torch
-    ms = (ctypes.c_float * 9)()
+    ms = (ctypes.c_float * 10)()
     nw, mode = ctypes.c_int(), ctypes.c_int()
     _check(library().hp_autotune_blocked(s.handle, _ptr(ws, torch.uint8, None, "workspace"), seq_lo,
                                          n_seq, repeats, ms, ctypes.byref(nw), ctypes.byref(mode),
@@ -278,6 +281,25 @@ def hp_enumerate_symmetric_blocked(s: Structures, ws, b_lo: int, b_hi: int, out=
         _ptr(designability, torch.int64, s.n_class, "designability"),
         _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)),
         "hp_enumerate_symmetric_blocked")
+
+
+def hp_wide_block_count(s: Structures) -> int:
+    return int(library().hp_wide_block_count(s.handle))
+
+
+def hp_enumerate_symmetric_wide(s: Structures, ws, b_lo: int, b_hi: int, out=None, emin=None,
+                                designability=None, nondesign=None, stream=None):
+    """Canonical wide blocks [b_lo, b_hi) (1024 sequences each); out / emin
+    are full 2^N maps indexed by sequence (written at s and, off the
+    diagonal, at reverse(s))."""
+    import torch
+    n = 1 << s.N
+    _check(library().hp_enumerate_symmetric_wide(
+        s.handle, _ptr(ws, torch.uint8, None, "workspace"), b_lo, b_hi,
+        _ptr(out, _U16, n, "out"), _ptr(emin, torch.int32, n, "emin"),
+        _ptr(designability, torch.int64, s.n_class, "designability"),
+        _ptr(nondesign, torch.int64, 1, "nondesign"), _stream_handle(stream)),
+        "hp_enumerate_symmetric_wide")
 
 
 def hp_enumerate_gap(s: Structures, ws, form: int, seq_lo: int, seq_hi: int, threshold: int = 1,
@@ -311,8 +333,8 @@ def hp_sample(s: Structures, ws, form: int, seed: int, idx_lo: int, idx_hi: int,
 
 def hp_blocked_select(nw: int, mode: int = -1):
     """Launch shape of the blocked int8 form: waves per workgroup (2, 4 or 8)
-    and staging mode (0 double-buffered, 1 pipelined, 2 operand in LDS, -1 by
-    product depth)."""
+    and staging mode (0 double-buffered, 1 pipelined, 2 operand in LDS, 3 wide
+    blocks of 1024 sequences (nw 4), -1 by product depth)."""
     _check(library().hp_blocked_select(nw, mode), "hp_blocked_select")
 
 

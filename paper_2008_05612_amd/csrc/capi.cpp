@@ -65,10 +65,13 @@ hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, c
                                          "within int8 and, with unary rows, depth <= 256");
         kb_max = std::max(kb_max, int(jobs[i].structs->K_pad / 32));
     }
-    // blocked jobs group by depth and by whether they carry unary rows
+    // blocked jobs group by depth, by whether they carry unary rows and by
+    // whether they run as wide blocks: key 4 depth + 2 wide + unary
     auto depth = [&](int i) {
         const hp_structs *t = jobs[i].structs;
-        return int(blocked ? 2 * t->blk_KB + (t->blk_coefB != 0 ? 1u : 0u) : t->K_pad / 32);
+        return int(blocked ? 4 * t->blk_KB + (blk_batch_wide(t) ? 2u : 0u) +
+                                 (t->blk_coefB != 0 ? 1u : 0u)
+                           : t->K_pad / 32);
     };
     // stable insertion sort by depth (batches hold a handful of jobs)
     for (int r = 0; r < njobs; ++r) {
@@ -83,7 +86,9 @@ hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, c
     for (int r = 0; r < njobs; ++r) {
         const hp_job &jb = jobs[order[r]];
         uint64_t items;
-        if (blocked) {
+        if (blocked && blk_batch_wide(jb.structs)) {
+            items = ((jb.seq_hi - 1) >> kWideBits) - (jb.seq_lo >> kWideBits) + 1;
+        } else if (blocked) {
             const uint64_t nblk = ((jb.seq_hi - 1) >> kBlkBits) - (jb.seq_lo >> kBlkBits) + 1;
             const uint64_t per = blk_batch_seqs_per_item() >> kBlkBits;
             items = (nblk + per - 1) / per;
@@ -129,8 +134,8 @@ hipError_t launch_plan(const BatchGroup *groups, int ngroups, int form, void *d_
         if (g.item_hi <= g.item_lo)
             continue;
         hipError_t e = form == HP_FORM_BLOCKED_I8
-                           ? launch_gemm_blk_batch(d_batch_ws, g.kb >> 1, (g.kb & 1) != 0,
-                                                   g.item_lo, g.item_hi, st)
+                           ? launch_gemm_blk_batch(d_batch_ws, g.kb >> 2, (g.kb & 1) != 0,
+                                                   (g.kb & 2) != 0, g.item_lo, g.item_hi, st)
                            : launch_gemm_batch(d_batch_ws, g.kb, g.item_lo, g.item_hi, st);
         if (e != hipSuccess)
             return e;
@@ -199,6 +204,7 @@ EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
     j.masks = reinterpret_cast<const uint32_t *>(base + s->ws.masks);
     j.gemm_a = reinterpret_cast<const int8_t *>(base + s->ws.gemm_a);
     j.gemm_b = reinterpret_cast<const int8_t *>(base + s->ws.gemm_b);
+    j.wide_s2 = s->wide_ok ? reinterpret_cast<const int8_t *>(base + s->ws.wide_s2) : nullptr;
     j.blk_shift = int32_t(s->blk_shift);
     j.blk_win_tiles = int32_t(s->blk_win_tiles);
     j.blk_coef = s->blk_coef;
@@ -348,6 +354,7 @@ hp_status hp_upload(const hp_structs *s, void *d_ws, size_t ws_bytes, void *stre
         {s->ws.gemm_a, s->gemm_a.data(), s->gemm_a.size()},
         {s->ws.gemm_b, s->gemm_b.data(), s->gemm_b.size()},
         {s->ws.blk_s2, s->blk_s2.data(), s->blk_s2.size()},
+        {s->ws.wide_s2, s->wide_s2.data(), s->wide_s2.size()},
     };
     for (const Part &p : parts) {
         if (!p.bytes)
@@ -529,6 +536,47 @@ hp_status hp_enumerate_symmetric_blocked(const hp_structs *s, const void *d_ws, 
         hipError_t e = launch_gemm_blocked(j, blocked_selected_nw(), blocked_selected_mode(), hs);
         if (e != hipSuccess)
             return device_fail(e, "hp_enumerate_symmetric_blocked launch");
+        lo = hi;
+    }
+    return HP_OK;
+}
+
+uint64_t hp_wide_block_count(const hp_structs *s)
+{
+    if (!s || !s->wide_ok)
+        return 0;
+    const int odd = s->N & 1;
+    const int h = (s->N - kWideBits - odd) / 2;
+    const uint64_t tri = h ? (uint64_t(1) << (h - 1)) * ((uint64_t(1) << h) + 1) : 1;
+    return tri * (odd ? 2 : 1);
+}
+
+hp_status hp_enumerate_symmetric_wide(const hp_structs *s, const void *d_ws, uint64_t b_lo,
+                                      uint64_t b_hi, uint16_t *d_out, int32_t *d_emin,
+                                      uint64_t *d_designability, uint64_t *d_nondesign,
+                                      void *stream)
+{
+    if (!s)
+        return fail(HP_EINVAL, "structures handle is NULL");
+    if (!d_ws)
+        return fail(HP_EINVAL, "workspace pointer is NULL");
+    if (!s->wide_ok)
+        return fail(HP_EUNSUPPORTED, "wide blocks need pure pair energies, N >= 10 and "
+                                     "per-block bytes within int8");
+    if (b_lo >= b_hi)
+        return fail(HP_EINVAL, "empty block range (b_lo >= b_hi)");
+    if (b_hi > hp_wide_block_count(s))
+        return fail(HP_EINVAL, "b_hi exceeds the number of canonical wide blocks");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    constexpr uint64_t kChunk = kBlockSeqs >> kWideBits;   // canonical wide blocks per launch
+    for (uint64_t lo = b_lo; lo < b_hi;) {
+        const uint64_t hi = b_hi - lo > kChunk ? lo + kChunk : b_hi;
+        EnumJob j = make_enum_job(s, d_ws, lo, hi, d_out, d_emin, d_designability, d_nondesign);
+        j.mode = kSeqCanonical;
+        j.half_bits = (s->N - kWideBits - (s->N & 1)) / 2;
+        hipError_t e = launch_gemm_wide_canonical(j, hs);
+        if (e != hipSuccess)
+            return device_fail(e, "hp_enumerate_symmetric_wide launch");
         lo = hi;
     }
     return HP_OK;

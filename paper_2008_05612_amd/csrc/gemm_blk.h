@@ -280,11 +280,15 @@ __device__ __forceinline__ void stage_two(const v4i &a2, const v4i (&sf)[S2_LDS 
             acc[(t + 1) & 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                 a2, S2_LDS ? s2[(t + 1) * 64 + lane] : sf[S2_LDS ? 0 : t + 1], zero, 0, 0, 0);
         const v16i &a = acc[t & 1];
-        if (__any(max16(a) >= thr[t])) {
+        if (__builtin_expect(__any(max16(a) >= thr[t]), 0)) {
+            // top-2 of the 16 window keys (one window, so their order is the
+            // global keys' order), then only those two become global keys
+            int b = 0, sc = 0;
 #pragma unroll
             for (int r = 0; r < 16; r += 2)
-                top2_add2(gb[t], gs[t], window_to_global(a[r], conf_base, win_shift),
-                          window_to_global(a[r + 1], conf_base, win_shift));
+                top2_add2(b, sc, a[r], a[r + 1]);
+            top2_merge(gb[t], gs[t], window_to_global(b, conf_base, win_shift),
+                       window_to_global(sc, conf_base, win_shift));
             thr[t] = absorb_threshold(gs[t], win_shift);
         }
     }
@@ -460,10 +464,313 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk_batch(BatchHeader *hdr, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wide blocks: 1024 sequences sharing every monomer above the low 10 (plain
+// ranges, pure pair energies), one per workgroup of 4 waves.  Wave w scores
+// the 256 sequences whose monomers 8 and 9 are the bits of w; the block
+// term, the weights w_v of the 10 varying monomers and their 16 pair terms
+// fill 29 of the 32 virtual rows, so ONE first product per conformation tile
+// serves all four waves: each wave computes it for every fourth tile (one
+// group of 4 tiles ahead) and hands the packed result to the others through
+// LDS.  Per 32 x 32 tile the matrix pipe runs one depth-32 product plus a
+// quarter of the first product's K_pad/32, and the first product is packed
+// once per workgroup instead of once per wave.
+// ---------------------------------------------------------------------------
+
+constexpr int kWideRowVV = 11, kWideRowIdx = 27;
+
+// Varying monomer x (0 .. 9) of a wide block: the low 10 for plain ranges;
+// for reversal-canonical blocks the 10 around the middle, h = j.half_bits
+// outer monomers on each side (and, for odd N, the middle monomer h + 5
+// outer as well).
+template <bool CANON>
+__device__ __forceinline__ int wide_pos(const EnumJob &j, int x)
+{
+    return CANON ? j.half_bits + x + (x >= 5 ? (j.N & 1) : 0) : x;
+}
+
+template <bool CANON>
+__device__ __forceinline__ bool wide_varies(const EnumJob &j, int i)
+{
+    if (!CANON)
+        return i < kWideBits;
+    const int h = j.half_bits, odd = j.N & 1;
+    return i >= h && i < h + kWideBits + odd && !(odd && i == h + 5);
+}
+
+// Pair p (0 .. 15) of the block's varying monomers as x-indices a | b << 4.
+template <bool CANON>
+__device__ __forceinline__ int wide_pair(const EnumJob &j, int p)
+{
+    const uint64_t w = (CANON && (j.N & 1)) ? (p < 8 ? kMid10OddPairs0 : kMid10OddPairs1)
+                                             : (p < 8 ? kLow10Pairs0 : kLow10Pairs1);
+    return int((w >> (8 * (p & 7))) & 0xffu);
+}
+
+// First-product A operand of a wide block, fragment kb of this lane:
+// virtual row m (0 block term, 1 .. 10 the weight of varying monomer m - 1,
+// 11 .. 26 the varying pairs, 27 and 28 the index rows) over product rows
+// k = 32 kb + 16 half + q of C1.
+template <bool CANON>
+__device__ __forceinline__ v4i wide_v_fragment(const EnumJob &j, uint64_t outer, int m, int half,
+                                               int kb)
+{
+    const int N = j.N;
+    const int coef = j.blk_coef;
+    const int wv = m >= 1 && m < kWideRowVV ? wide_pos<CANON>(j, m - 1) : -1;
+    int va = -1, vb = -1;
+    if (m >= kWideRowVV && m < kWideRowIdx) {
+        const int pr = wide_pair<CANON>(j, m - kWideRowVV);
+        va = wide_pos<CANON>(j, pr & 15);
+        vb = wide_pos<CANON>(j, pr >> 4);
+    }
+    // product row k < K is the pair (i, i + d) of the k-th odd separation
+    // d >= 3 in (d, i) order
+    const int kbase = kb * 32 + half * 16;
+    int d = 3, i = kbase;
+    while (d < N && i >= N - d) {
+        i -= N - d;
+        d += 2;
+    }
+    uint32_t w[4];
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            const int k = kbase + q4 * 4 + bb;
+            int v = 0;
+            if (k == j.K) {
+                v = m == kWideRowIdx ? 1 : 0;
+            } else if (k == j.K + 1) {
+                v = m == kWideRowIdx + 1 ? -1 : 0;
+            } else if (d < N) {
+                const int jj = i + d;
+                const bool out_i = !wide_varies<CANON>(j, i), out_j = !wide_varies<CANON>(j, jj);
+                const bool h_i = (outer >> i) & 1u, h_j = (outer >> jj) & 1u;
+                if (m == 0)
+                    v = out_i && out_j && h_i && h_j ? -coef : 0;
+                else if (m < kWideRowVV)
+                    v = (i == wv && out_j && h_j) || (jj == wv && out_i && h_i) ? -coef : 0;
+                else if (m < kWideRowIdx)
+                    v = i == va && jj == vb ? -coef : 0;
+            }
+            word |= (uint32_t(v) & 0xffu) << (8 * bb);
+            ++i;   // next row: next i, or the next run
+            if (d < N && i + d >= N) {
+                i = 0;
+                d += 2;
+            }
+        }
+        w[q4] = word;
+    }
+    return v4i{int(w[0]), int(w[1]), int(w[2]), int(w[3])};
+}
+
+// Canonical wide block index t -> outer bits, as blk_canonical_outer with 10
+// varying monomers: (a, m, b) = high h, middle (odd N), low h bits; the
+// canonical blocks are a <= b' = reverse_h(b), indexed over m, then row pairs
+// p < 2^(h-1) holding row b' = p (a = 0 .. p) and row b' = 2^h - 1 - p
+// (a = 0 .. 2^h - 1 - p).  *diag: a == b', the block is its own reverse.
+__device__ __forceinline__ uint64_t wide_canonical_outer(const EnumJob &j, uint64_t t64, bool *diag)
+{
+    const int h = j.half_bits;
+    const int odd = j.N & 1;
+    const uint32_t t = uint32_t(t64);
+    const uint32_t side = 1u << h;
+    const uint32_t span = side + 1;
+    const uint32_t per_m = h ? (side >> 1) * span : 1;
+    const uint32_t m = t / per_m;
+    const uint32_t r = t - m * per_m;
+    const uint32_t p = h ? r / span : 0;
+    const uint32_t o = r - p * span;
+    const bool first = o <= p;
+    const uint32_t bp = first ? p : side - 1 - p;
+    const uint32_t a = first ? o : o - p - 1;
+    *diag = a == bp;
+    const uint32_t b = h ? (__builtin_bitreverse32(bp) >> (32 - h)) : 0;
+    return (uint64_t(a) << (h + kWideBits + odd)) | (uint64_t(m) << (h + 5)) | b;
+}
+
+// One wide block for the workgroup's four waves: plain block `blk` (the 1024
+// sequences blk * 1024 + x) or canonical block `blk`; vlds holds KB * 64
+// vectors, a2s two groups of 4 packed first products.
+template <int KB, bool CANON>
+__device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *vlds,
+                                          v4i (*a2s)[4][64])
+{
+    bool diag = false;
+    const uint64_t outer = CANON ? wide_canonical_outer(j, blk, &diag) : blk << kWideBits;
+    // Contact tiles of the first product are loaded one group ahead into
+    // registers for shallow products; deep ones (K_pad > 192) load right
+    // before use, which keeps four waves per SIMD.
+    constexpr bool kPrefetch = KB <= 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const v4i *__restrict__ B1 = reinterpret_cast<const v4i *>(j.gemm_b);
+
+    // the four waves build the block's fragments, one kb at a time
+    for (int kb = wave; kb < KB; kb += 4)
+        vlds[kb * 64 + lane] = wide_v_fragment<CANON>(j, outer, col, half, kb);
+    v4i sf[kBlkTiles];
+    const v4i *__restrict__ S2 = reinterpret_cast<const v4i *>(j.wide_s2) +
+                                 ((CANON ? 4 : 0) + wave) * (kBlkTiles * 64);
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t)
+        sf[t] = S2[t * 64 + lane];
+
+    int gb[kBlkTiles], gs[kBlkTiles], thr[kBlkTiles];
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t)
+        gb[t] = gs[t] = thr[t] = 0;
+
+    const int n_tiles = j.n_tiles;
+    const int win_tiles = j.blk_win_tiles;
+    const int win_shift = j.blk_shift;
+
+    // contact tile `tile` of the first product (this lane's fragments); every
+    // wave reads only its own tiles, straight from global memory (L2-resident)
+    auto load_c1 = [&](int tile, v4i (&c1)[KB]) {
+        const v4i *__restrict__ src = B1 + size_t(tile) * (KB * 64) + lane;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+            c1[kb] = src[kb * 64];
+    };
+    // first product of a tile into this wave's slot of buffer `buf`
+    auto first = [&](const v4i (&c1)[KB], int buf) {
+        v16i d1;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            const v16i zero = {};
+            d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(vlds[kb * 64 + lane], c1[kb],
+                                                       kb == 0 ? zero : d1, 0, 0, 0);
+        }
+        a2s[buf][wave][lane] = pack_d1(d1);
+    };
+
+    v4i c1[KB];
+    __syncthreads();   // vlds
+    if (wave < n_tiles) {
+        load_c1(wave, c1);
+        first(c1, 0);
+    }
+    if (kPrefetch && 4 + wave < n_tiles)
+        load_c1(4 + wave, c1);
+    __syncthreads();
+    int conf_base = 0;
+    int wnext = win_tiles;   // first tile of the next key window
+    for (int g = 0; g * 4 < n_tiles; ++g) {
+        const int buf = g & 1;
+        const int nt = (g + 1) * 4 + wave;   // this wave's tile of the next group
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const int tile = g * 4 + tt;
+            if (tile < n_tiles) {
+                if (tile == wnext) {
+                    conf_base += win_tiles * kTileConf;
+                    wnext += win_tiles;
+                }
+                stage_two<false>(a2s[buf][tt][lane], sf, nullptr, lane, gb, gs, thr, conf_base,
+                                 win_shift);
+            }
+            if (tt == 0 && nt < n_tiles) {
+                if (!kPrefetch)
+                    load_c1(nt, c1);
+                first(c1, buf ^ 1);
+                if (kPrefetch && nt + 4 < n_tiles)
+                    load_c1(nt + 4, c1);
+            }
+        }
+        // the next group's first products are visible, and this group's
+        // buffer is free for the group after it
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t) {
+        const int ob = __shfl_xor(gb[t], 32);
+        const int os = __shfl_xor(gs[t], 32);
+        top2_merge(gb[t], gs[t], ob, os);
+        const int x = wave * 256 + t * 32 + col;
+        if constexpr (CANON) {
+            // off the diagonal the block's reverse is never scored: write both;
+            // a diagonal block holds each sequence and its reverse itself
+            uint64_t sq = outer;
+#pragma unroll
+            for (int b = 0; b < kWideBits; ++b)
+                sq |= uint64_t((x >> b) & 1) << wide_pos<true>(j, b);
+            const uint64_t rs = diag ? sq : __builtin_bitreverse64(sq) >> (64 - j.N);
+            finish_sequence(j, sq, sq, rs, half == 0 && blk < j.hi, gb[t], gs[t], lane == 0, 1);
+        } else {
+            const uint64_t idx = outer + uint64_t(x);
+            finish_sequence(j, idx, idx, idx, half == 0 && idx >= j.lo && idx < j.hi, gb[t],
+                            gs[t], lane == 0, 1);
+        }
+    }
+}
+
+template <int KB, bool CANON>
+__global__ __launch_bounds__(256) void k_gemm_wide(EnumJob j)
+{
+    // first-product A operand of the block (the same for all four waves) and
+    // the packed first products of the current and the next group of 4 tiles
+    __shared__ v4i vlds[KB * 64];
+    __shared__ v4i a2s[2][4][64];
+    wide_body<KB, CANON>(j, (CANON ? j.lo : j.lo >> kWideBits) + blockIdx.x, vlds, a2s);
+}
+
+// Batched wide blocks for jobs of one product depth: workgroup b scores the
+// wide block of item item_lo + b, in the job whose item range holds it.
 template <int KB>
-hipError_t launch_blk_batch_kb(BatchHeader *hdr, int item_lo, unsigned grid, bool unary,
+__global__ __launch_bounds__(256) void k_gemm_wide_batch(BatchHeader *hdr, int item_lo)
+{
+    __shared__ v4i vlds[KB * 64];
+    __shared__ v4i a2s[2][4][64];
+    const EnumJob *jobs = reinterpret_cast<const EnumJob *>(hdr + 1);
+    const int njobs = hdr->njobs;
+    const int64_t *start = reinterpret_cast<const int64_t *>(jobs + njobs);
+    const int it = item_lo + int(blockIdx.x);
+    int lo = 0, hi = njobs - 1;   // job with start[job] <= it < start[job+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (start[mid] <= it)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const EnumJob &j = jobs[lo];
+    wide_body<KB, false>(j, (j.lo >> kWideBits) + uint64_t(it - start[lo]), vlds, a2s);
+}
+
+template <int KB>
+hipError_t launch_wide_batch(BatchHeader *hdr, int item_lo, unsigned grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_gemm_wide_batch<KB>), dim3(grid), dim3(256), 0, st, hdr, item_lo);
+    return hipGetLastError();
+}
+
+template <int KB>
+hipError_t launch_wide(const EnumJob &j, hipStream_t st)
+{
+    if (j.mode == kSeqCanonical) {
+        hipLaunchKernelGGL((k_gemm_wide<KB, true>), dim3(unsigned(j.hi - j.lo)), dim3(256), 0, st,
+                           j);
+    } else {
+        const uint64_t n = ((j.hi - 1) >> kWideBits) - (j.lo >> kWideBits) + 1;
+        hipLaunchKernelGGL((k_gemm_wide<KB, false>), dim3(unsigned(n)), dim3(256), 0, st, j);
+    }
+    return hipGetLastError();
+}
+
+template <int KB>
+hipError_t launch_blk_batch_kb(BatchHeader *hdr, int item_lo, unsigned grid, bool unary, bool wide,
                                hipStream_t st)
 {
+    if (wide)
+        return unary ? hipErrorInvalidValue : launch_wide_batch<KB>(hdr, item_lo, grid, st);
     constexpr int MODE = KB <= 6 ? kBlkLdsS2 : kBlkLds;
     if constexpr (KB <= kBlkUnaryMaxKB) {
         if (unary) {
@@ -518,6 +825,8 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
 {
     if (j.blk_ngroups > 0 || j.blk_coefB != 0)
         return launch_blk_unary<KB>(j, st);
+    if (mode == kBlkStageWide)
+        return launch_wide<KB>(j, st);
     if (mode == kBlkLdsS2) {
         switch (nw) {
         case 2: return launch_blk_shape<KB, 2, kBlkLdsS2>(j, st);
@@ -549,9 +858,13 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
         return launch_blk<KB>(j, nw, mode, st);                                           \
     }                                                                                     \
     hipError_t launch_gemm_blk_batch_kb##KB(BatchHeader *hdr, int item_lo, unsigned grid,  \
-                                            bool unary, hipStream_t st)                   \
+                                            bool unary, bool wide, hipStream_t st)        \
     {                                                                                     \
-        return launch_blk_batch_kb<KB>(hdr, item_lo, grid, unary, st);                    \
+        return launch_blk_batch_kb<KB>(hdr, item_lo, grid, unary, wide, st);              \
+    }                                                                                     \
+    hipError_t launch_gemm_wide_kb##KB(const EnumJob &j, hipStream_t st)                  \
+    {                                                                                     \
+        return launch_wide<KB>(j, st);                                                    \
     }
 
 }  // namespace hpmap

@@ -35,6 +35,7 @@ struct WsLayout {
     size_t gemm_a = 0;   // int8_t[n_tiles][K_pad/32][64 lanes][16]
     size_t gemm_b = 0;   // blocked form: int8_t[n_tiles][K_pad/32][64 lanes][16], or none
     size_t blk_s2 = 0;   // blocked form: int8_t[2 geometries][8 tiles][64 lanes][16], or none
+    size_t wide_s2 = 0;  // wide blocks: int8_t[2 geometries][4 waves][8 tiles][64 lanes][16], or none
     size_t total = 0;
 };
 
@@ -71,6 +72,8 @@ struct hp_structs {
     std::vector<int8_t> gemm_a;       // int8 contact matrix in MFMA A-operand order
     std::vector<int8_t> gemm_b;       // blocked form: 0/1 contact matrix + window index rows
     std::vector<int8_t> blk_s2;       // blocked form: per-sequence operand of the second product
+    bool wide_ok = false;             // wide blocks apply (pure pair energies, N >= 10)
+    std::vector<int8_t> wide_s2;      // wide blocks: per-sequence operand of the second product
     std::vector<uint8_t> pair_rows;   // K_pad * 4: (i, j, constant, 0) per product row
     hpmap::WsLayout ws;
 };
@@ -87,6 +90,22 @@ namespace hpmap {
 constexpr uint64_t kLow8Pairs = 0x6372526141705030ull;   // (0,3) (0,5) (0,7) (1,4) (1,6) (2,5) (2,7) (3,6)
 constexpr int kLow8Pair8 = 0x74;                          // (4,7)
 constexpr int kLow8NumPairs = 9;
+
+// Wide blocks of the blocked form: 2^kWideBits = 1024 sequences sharing
+// every monomer above the low 10, scored by the 4 waves of one workgroup.
+// Pairs of the low 10 monomers with odd separation >= 3, as x-indices
+// a | b << 4 a byte each: pairs 0 .. 7 in kLow10Pairs0, 8 .. 15 in
+// kLow10Pairs1 (shared by the host tables and the kernel).
+constexpr int kWideBits = 10;
+constexpr uint64_t kLow10Pairs0 = 0x5096857463524130ull;   // (0,3) (1,4) (2,5) (3,6) (4,7) (5,8) (6,9) (0,5)
+constexpr uint64_t kLow10Pairs1 = 0x9092817094837261ull;   // (1,6) (2,7) (3,8) (4,9) (0,7) (1,8) (2,9) (0,9)
+constexpr int kLow10NumPairs = 16;
+// Reversal-canonical wide blocks vary the 10 monomers around the middle:
+// pos(x) = h + x for even N; for odd N the middle monomer h + 5 stays outer,
+// pos(x) = h + x + (x >= 5).  With even N the pairs are those of the low 10;
+// with odd N (x-indices, same byte layout):
+constexpr uint64_t kMid10OddPairs0 = 0x7151806096854130ull;  // (0,3) (1,4) (5,8) (6,9) (0,6) (0,8) (1,5) (1,7)
+constexpr uint64_t kMid10OddPairs1 = 0x8464937353826291ull;  // (1,9) (2,6) (2,8) (3,5) (3,7) (3,9) (4,6) (4,8)
 
 struct BlockGeometry {
     int pos[8];
@@ -110,7 +129,7 @@ EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
 // start[njobs + 1] and groups[njobs] are scratch and launch groups supplied
 // by the caller (nothing is allocated).
 struct BatchGroup {
-    int kb, item_lo, item_hi;   // product depth (blocked: 2 depth + unary flag), its items
+    int kb, item_lo, item_hi;   // product depth (blocked: 4 depth + 2 wide + unary), its items
 };
 hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, char *host,
                      int *order, int64_t *start, BatchGroup *groups, int *ngroups);

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+struct hp_structs;
+
 namespace hpmap {
 
 // One enumeration job as the kernels see it.  Plain data, copied into kernel
@@ -41,6 +43,8 @@ struct EnumJob {
     int32_t blk_KB, blk_coefB, blk_ngroups;   // first-product depth / 32, m2 B, unary rows
     uint64_t blk_grp[3];                      // unary group of each outer monomer (4 bits)
     const int8_t *blk_s2;           // second-product operand of this geometry (8 x 64 x 16 B)
+    const int8_t *wide_s2;          // wide blocks: second-product operand (4 x 8 x 64 x 16 B),
+                                    // or null where wide blocks do not apply
 };
 
 // Index -> sequence maps of a job.  kSeqPlain: index t is sequence t.
@@ -84,14 +88,21 @@ hipError_t launch_popcount(const EnumJob &j, hipStream_t st);
 // buffered LDS with the next tile's first product overlapping this tile's
 // key updates.
 hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t st);
+// Reversal-canonical wide blocks [j.lo, j.hi) (j.mode kSeqCanonical,
+// j.half_bits the outer monomers on each side).
+hipError_t launch_gemm_wide_canonical(const EnumJob &j, hipStream_t st);
 // Staging modes of the blocked form's contact tiles (gemm_blk.h); mode < 0
 // picks by product depth.
-enum BlkStage { kBlkStageLds = 0, kBlkStagePipe = 1, kBlkStageS2Lds = 2 };
-// Persistent batched launch of the blocked form (plain jobs): items of
-// blk_batch_seqs_per_item() sequences (4 blocks), same work-list layout.
+// kBlkStageWide: wide blocks of 1024 sequences per workgroup of 4 waves,
+// the first product shared by the waves (pure pair energies, plain ranges).
+enum BlkStage { kBlkStageLds = 0, kBlkStagePipe = 1, kBlkStageS2Lds = 2, kBlkStageWide = 3 };
+// Batched launch of the blocked form (plain jobs), same work-list layout:
+// items of blk_batch_seqs_per_item() sequences, one wide block (wide jobs:
+// blk_batch_wide) or 4 blocks of 256, one workgroup per item.
 uint64_t blk_batch_seqs_per_item();
-hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, int item_lo, int item_hi,
-                                 hipStream_t st);
+bool blk_batch_wide(const hp_structs *s);
+hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, bool wide, int item_lo,
+                                 int item_hi, hipStream_t st);
 // Process-wide launch shape of the blocked form (runtime.cpp).
 int blocked_selected_nw();
 int blocked_selected_mode();

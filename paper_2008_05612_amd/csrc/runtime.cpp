@@ -144,8 +144,10 @@ hp_status hp_blocked_select(int nw, int mode)
 {
     if (nw != 2 && nw != 4 && nw != 8)
         return fail(HP_EINVAL, "blocked form: waves per workgroup must be 2, 4 or 8");
-    if (mode < -1 || mode > 2)
-        return fail(HP_EINVAL, "blocked form: staging mode must be -1, 0, 1 or 2");
+    if (mode < -1 || mode > 3)
+        return fail(HP_EINVAL, "blocked form: staging mode must be -1, 0, 1, 2 or 3");
+    if (mode == 3 && nw != 4)
+        return fail(HP_EINVAL, "blocked form: wide blocks (mode 3) run 4 waves per workgroup");
     g_blocked_nw.store(nw);
     g_blocked_mode.store(mode);
     return HP_OK;
@@ -281,8 +283,14 @@ hp_status hp_autotune_blocked(const hp_structs *s, const void *d_ws, uint64_t se
     int bi = -1;
     float best_t = 0.f;
     EnumJob j = make_enum_job(s, d_ws, seq_lo, seq_lo + n_seq, nullptr, nullptr, nullptr, nullptr);
-    for (int i = 0; i < 9 && err == hipSuccess; ++i) {
-        const int nw = kNW[i / 3], mode = i % 3;
+    for (int i = 0; i < 10 && err == hipSuccess; ++i) {
+        // shapes 0 .. 8: nw x staging mode; shape 9: wide blocks, where they apply
+        const int nw = i < 9 ? kNW[i / 3] : 4, mode = i < 9 ? i % 3 : 3;
+        if (i == 9 && !(s->wide_ok && j.blk_ngroups == 0 && j.blk_coefB == 0)) {
+            if (ms)
+                ms[i] = -1.f;
+            continue;
+        }
         err = launch_gemm_blocked(j, nw, mode, st);   // warm-up
         if (err == hipSuccess)
             err = hipEventRecord(e0, st);
@@ -309,12 +317,13 @@ hp_status hp_autotune_blocked(const hp_structs *s, const void *d_ws, uint64_t se
         (void)hipEventDestroy(e1);
     if (err != hipSuccess)
         return fail(HP_EDEVICE, std::string("hp_autotune_blocked: ") + hipGetErrorString(err));
-    g_blocked_nw.store(kNW[bi / 3]);
-    g_blocked_mode.store(bi % 3);
+    const int bnw = bi < 9 ? kNW[bi / 3] : 4, bmode = bi < 9 ? bi % 3 : 3;
+    g_blocked_nw.store(bnw);
+    g_blocked_mode.store(bmode);
     if (best_nw)
-        *best_nw = kNW[bi / 3];
+        *best_nw = bnw;
     if (best_mode)
-        *best_mode = bi % 3;
+        *best_mode = bmode;
     return HP_OK;
 }
 

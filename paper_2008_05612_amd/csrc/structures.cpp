@@ -677,6 +677,75 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
         }
     }
 
+    // Wide blocks (pure pair energies), two geometries: plain (the low 10
+    // monomers vary) and reversal-canonical (the 10 around the middle; see
+    // hp_internal.h).  Wave w of the workgroup holds the 256 sequences whose
+    // varying monomers 8 and 9 are the bits of w.  Same first-product matrix
+    // and key scale as above; the virtual rows are m = 0 the block term,
+    // 1 .. 10 the weight of varying monomer m - 1, 11 .. 26 the varying pairs
+    // (kLow10Pairs, or kMid10OddPairs for odd N canonical), 27 and 28 the
+    // index bytes.  Lane l of tile t of wave w holds block sequence
+    // x = 256 w + 32 t + (l & 31) and its byte q the indicator of row
+    // m = 8 (q / 4) + 4 (l / 32) + q % 4.
+    s->wide_ok = false;
+    s->wide_s2.clear();
+    const int wodd = N & 1;
+    const int whalf = N >= kWideBits ? (N - kWideBits - wodd) / 2 : 0;
+    auto wide_pos = [&](int g, int x) { return g == 0 ? x : whalf + x + (x >= 5 ? wodd : 0); };
+    auto wide_pair = [&](int g, int p) {
+        const uint64_t w = (g == 1 && wodd) ? (p < 8 ? kMid10OddPairs0 : kMid10OddPairs1)
+                                            : (p < 8 ? kLow10Pairs0 : kLow10Pairs1);
+        return int((w >> (8 * (p & 7))) & 0xffu);
+    };
+    if (s->blk_ok && B == 0 && N >= kWideBits) {
+        int maxw = 0;   // largest weight of a varying monomer (all outer monomers H)
+        for (int g = 0; g < 2; ++g) {
+            bool vary[64] = {};
+            for (int x = 0; x < kWideBits; ++x)
+                vary[wide_pos(g, x)] = true;
+            for (int x = 0; x < kWideBits; ++x) {
+                const int v = wide_pos(g, x);
+                for (uint32_t c = 0; c < n_conf; ++c) {
+                    int with_outer = 0;
+                    for (uint32_t q = 0; q < s->nbp; ++q) {
+                        const int a = s->contacts[(size_t(c) * s->nbp + q) * 2];
+                        const int b = s->contacts[(size_t(c) * s->nbp + q) * 2 + 1];
+                        with_outer += (a == v && !vary[b]) || (b == v && !vary[a]);
+                    }
+                    maxw = std::max(maxw, int(A) * with_outer);
+                }
+            }
+        }
+        s->wide_ok = int64_t(s->blk_coef) * maxw <= 128;
+    }
+    if (s->wide_ok) {
+        s->wide_s2.assign(2 * 4 * 8 * 64 * 16, 0);
+        for (int g = 0; g < 2; ++g)
+            for (int w = 0; w < 4; ++w)
+                for (int t = 0; t < 8; ++t)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int x = 256 * w + 32 * t + (lane & 31), half = lane >> 5;
+                        for (int q = 0; q < 16; ++q) {
+                            const int m = 8 * (q / 4) + 4 * half + q % 4;
+                            int v = 0;
+                            if (m == 0) {
+                                v = -128;
+                            } else if (m < 11) {
+                                v = ((x >> (m - 1)) & 1) ? -128 : 0;
+                            } else if (m < 27) {
+                                const int pr = wide_pair(g, m - 11);
+                                v = ((x >> (pr & 15)) & (x >> (pr >> 4)) & 1) ? -128 : 0;
+                            } else if (m == 27) {
+                                v = 1;
+                            } else if (m == 28) {
+                                v = -128;
+                            }
+                            s->wide_s2[(((size_t(g) * 4 + w) * 8 + t) * 64 + lane) * 16 + q] =
+                                static_cast<int8_t>(v);
+                        }
+                    }
+    }
+
     // pair table for the popcount form, 4 bytes per row (i, j, 0, 0)
     s->pair_rows.assign(size_t(s->K_pad) * 4, 0);
     for (uint32_t k = 0; k < s->K_pad; ++k) {
@@ -694,7 +763,8 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
     L.gemm_a = up(L.masks + s->masks.size() * 4);
     L.gemm_b = up(L.gemm_a + s->gemm_a.size());
     L.blk_s2 = up(L.gemm_b + s->gemm_b.size());
-    L.total = up(L.blk_s2 + s->blk_s2.size());
+    L.wide_s2 = up(L.blk_s2 + s->blk_s2.size());
+    L.total = up(L.wide_s2 + s->wide_s2.size());
     return HP_OK;
 }
 

@@ -13,7 +13,9 @@ s <= reverse(s) for the dense and popcount forms (hp_enumerate_symmetric),
 canonical blocks for the blocked form (hp_enumerate_symmetric_blocked); each
 result is written at both s and reverse(s), and the steps run over canonical
 indices.  The uint16 map stays resident on the device (2^36 x 2 B = 137 GB
-for 6x6) unless --no-map is given.  With --checkpoint, the accumulated
+for 6x6) unless --no-map is given.  With --symmetric and the blocked form the
+canonical blocks are wide (1024 sequences, hp_enumerate_symmetric_wide)
+where they apply.  With --checkpoint, the accumulated
 designability is written after every step and a rerun resumes after the last
 finished step (the map of skipped steps is then not available, so
 --neighbors is refused on a resumed run).  --phi builds the whole phi_pq
@@ -23,7 +25,8 @@ connected components of the phenotype graph (designable phenotypes joined
 when a single mutation links them).
 
 All device work goes through the C ABI (hp_enumerate, hp_enumerate_symmetric,
-hp_enumerate_symmetric_blocked, hp_neighbors, hp_phi_counts, hp_phi_sparse).
+hp_enumerate_symmetric_blocked, hp_enumerate_symmetric_wide, hp_neighbors,
+hp_phi_counts, hp_phi_sparse).
 """
 from __future__ import annotations
 
@@ -44,24 +47,26 @@ def _parse_lattice(text: str):
     return tuple(dims)
 
 
-def _load_checkpoint(path, dims, form, block_bits, n_class, symmetric, table):
+def _load_checkpoint(path, dims, form, block_bits, n_class, symmetric, table, geometry):
     if not path or not os.path.exists(path):
         return None
     with open(path) as f:
         ck = json.load(f)
     if (tuple(ck["dims"]) != dims or ck["form"] != form or ck["block_bits"] != block_bits
             or len(ck["designability"]) != n_class or ck.get("symmetric", False) != symmetric
-            or ck.get("table") != (list(table) if table else None)):
+            or ck.get("table") != (list(table) if table else None)
+            or ck.get("geometry", geometry) != geometry):
         raise ValueError("checkpoint %s is for another run" % path)
     return ck
 
 
-def _save_checkpoint(path, dims, form, block_bits, symmetric, table, next_block, desig,
+def _save_checkpoint(path, dims, form, block_bits, symmetric, table, geometry, next_block, desig,
                      nondesign):
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump({"dims": list(dims), "form": form, "block_bits": block_bits,
                    "symmetric": symmetric, "table": list(table) if table else None,
+                   "geometry": geometry,
                    "next_block": next_block,
                    "designability": [int(x) for x in desig], "nondesign": int(nondesign)}, f)
     os.replace(tmp, path)
@@ -83,21 +88,33 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
     total = 1 << N
     if form is None:
         form = hp.FORM_BLOCKED_I8 if hp.hp_canonical_block_count(s) else hp.FORM_GEMM_I8
-    blocked_sym = symmetric and form == hp.FORM_BLOCKED_I8
+    # the blocked form's canonical blocks: wide (1024 sequences, the first
+    # product shared by a workgroup) where they apply and the launch shape
+    # allows, else blocks of 256
+    wide_sym = (symmetric and form == hp.FORM_BLOCKED_I8 and hp.hp_wide_block_count(s) > 0
+                and hp.hp_blocked_selected() in ((4, -1), (4, 3)))
+    blocked_sym = symmetric and form == hp.FORM_BLOCKED_I8 and not wide_sym
     # indices to process: sequences, canonical sequences, or canonical blocks
-    # of 256 sequences; one step covers 2^block_bits sequences' worth
-    if blocked_sym:
+    # of 256 or 1024 sequences; one step covers 2^block_bits sequences' worth
+    if wide_sym:
+        space = hp.hp_wide_block_count(s)
+        block = 1 << max(0, min(block_bits, N) - 10)
+        per_index = 1024
+    elif blocked_sym:
         space = hp.hp_canonical_block_count(s)
         block = 1 << max(0, min(block_bits, N) - 8)
+        per_index = 256
     else:
         space = hp.hp_canonical_count(s) if symmetric else total
         block = 1 << min(block_bits, N)
-    per_index = 256 if blocked_sym else 1
+        per_index = 1
+    geometry = "wide" if wide_sym else ("blocks256" if blocked_sym else "sequences")
     n_blocks = (space + block - 1) // block
     desig = torch.zeros(s.n_class, dtype=torch.int64, device=device)
     nond = torch.zeros(1, dtype=torch.int64, device=device)
     start_block = 0
-    ck = _load_checkpoint(checkpoint, dims, form, block_bits, s.n_class, symmetric, table)
+    ck = _load_checkpoint(checkpoint, dims, form, block_bits, s.n_class, symmetric, table,
+                          geometry)
     if ck:
         start_block = ck["next_block"]
         desig.copy_(torch.tensor(np.array(ck["designability"], dtype=np.uint64).view(np.int64)))
@@ -113,7 +130,9 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
     for b in range(start_block, n_blocks):
         lo, hi = b * block, min((b + 1) * block, space)
         tb = time.time()
-        if blocked_sym:
+        if wide_sym:
+            hp.hp_enumerate_symmetric_wide(s, ws, lo, hi, out, None, desig, nond)
+        elif blocked_sym:
             hp.hp_enumerate_symmetric_blocked(s, ws, lo, hi, out, None, desig, nond)
         elif symmetric:
             hp.hp_enumerate_symmetric(s, ws, form, lo, hi, out, None, desig, nond)
@@ -122,7 +141,7 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
                             desig, nond)
         torch.cuda.synchronize()
         if checkpoint:
-            _save_checkpoint(checkpoint, dims, form, block_bits, symmetric, table, b + 1,
+            _save_checkpoint(checkpoint, dims, form, block_bits, symmetric, table, geometry, b + 1,
                              desig.cpu().numpy().view(np.uint64), int(nond.item()))
         progress("block %d/%d [%d, %d) %.2f s" % (b + 1, n_blocks, lo, hi, time.time() - tb))
     wall = time.time() - t0
@@ -132,7 +151,7 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
         "lattice": "x".join(str(x) for x in dims if x > 1) or "1",
         "N": N, "sequences": total, "n_conf": s.n_conf, "n_class": s.n_class,
         "form": {hp.FORM_GEMM_I8: "gemm_i8", hp.FORM_BLOCKED_I8: "blocked_i8"}.get(form, "popcount"),
-        "symmetric": symmetric, "scored_sequences": space * per_index,
+        "symmetric": symmetric, "geometry": geometry, "scored_sequences": space * per_index,
         "blocks": n_blocks, "block_sequences": block * per_index, "resumed_at_block": start_block,
         "wall_s": wall,
         "evals_per_s": (space - start_block * block) * per_index * s.n_conf / wall,
@@ -145,7 +164,11 @@ def run(dims, form=None, block_bits=30, keep_map=True, neighbors=False,
         "sum_check": int(d.sum()) + nd == total,
     }
     if out is not None and fill is not None:
-        summary["unwritten"] = int((out == fill).sum().item())
+        # counted in slices: a comparison over the whole 2^36-entry map at
+        # once would need tens of GB of temporaries
+        step = 1 << 28
+        summary["unwritten"] = sum(int(torch.count_nonzero(out[lo:lo + step] == fill).item())
+                                   for lo in range(0, total, step))
     if neighbors and out is not None:
         z = lambda n: torch.zeros(n, dtype=torch.int64, device=device)  # noqa: E731
         neu, dele, oth, row = z(s.n_class), z(s.n_class), z(s.n_class), z(s.n_class + 1)

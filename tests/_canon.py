@@ -1,6 +1,7 @@
 """Reversal bookkeeping shared by the GPU tests: the sequences of a
-canonical block of the blocked form, and bit reversal (index arithmetic
-only; nothing of the method's energies)."""
+canonical block of the blocked form (blocks of 256) or of a canonical wide
+block (1024), and bit reversal (index arithmetic only; nothing of the
+method's energies)."""
 import numpy as np
 
 
@@ -30,3 +31,32 @@ def canonical_block_sequences(N, t):
     b = int(reverse_bits(np.array([bp], dtype=np.uint64), h)[0])
     x = np.arange(256, dtype=np.uint64)
     return (np.uint64(a) << np.uint64(h + 8)) | (x << np.uint64(h)) | np.uint64(b), a == bp
+
+
+def canonical_wide_block_sequences(N, t):
+    """The 1024 sequences of canonical wide block t and whether the block is
+    its own reverse, from the block index order stated for
+    hp_enumerate_symmetric_wide: h = (N - 10 - N % 2) / 2 outer monomers on
+    each side (a high, b low, and for odd N the middle monomer m between the
+    two groups of 5 varying monomers), index over m, then row pairs p of the
+    (a, b') triangle; b = reverse_h(b')."""
+    odd = N & 1
+    h = (N - 10 - odd) // 2
+    side = 1 << h
+    span = side + 1
+    per_m = (side >> 1) * span if h else 1
+    m, r = divmod(t, per_m)
+    p = r // span if h else 0
+    o = r - p * span
+    if o <= p:
+        bp, a = p, o
+    else:
+        bp, a = side - 1 - p, o - p - 1
+    b = int(reverse_bits(np.array([bp], dtype=np.uint64), h)[0]) if h else 0
+    x = np.arange(1024, dtype=np.uint64)
+    outer = (a << (h + 10 + odd)) | (m << (h + 5)) | b
+    seqs = np.full(1024, outer, dtype=np.uint64)
+    for k in range(10):
+        pos = h + k + (odd if k >= 5 else 0)
+        seqs |= ((x >> np.uint64(k)) & np.uint64(1)) << np.uint64(pos)
+    return seqs, a == bp

@@ -155,7 +155,8 @@ def test_argument_errors(lib):
     heavy = hp.Structures(3, 3, 3, table=(0, -25, -25, -57))
     assert lib.hp_enumerate(heavy.handle, fake_ws, 2, 0, 16, None, None, None, None, None) == -5
     assert lib.hp_enumerate(s.handle, fake_ws, 3, 0, 16, None, None, None, None, None) == -1
-    assert lib.hp_blocked_select(3, 0) == -1 and lib.hp_blocked_select(4, 3) == -1
+    assert lib.hp_blocked_select(3, 0) == -1 and lib.hp_blocked_select(4, 4) == -1
+    assert lib.hp_blocked_select(2, 3) == -1      # wide blocks run 4 waves per workgroup
     assert lib.hp_autotune_blocked(tiny.handle, fake_ws, 0, 16, 1, None, None, None, None) == -5
     assert lib.hp_autotune_blocked(s.handle, fake_ws, 0, (1 << 16) + 1, 1, None, None, None,
                                    None) == -1
@@ -243,6 +244,70 @@ def test_canonical_block_count(lib):
     assert hp.hp_canonical_block_count(hp.Structures(2, 3, 1)) == 0
     assert hp.hp_canonical_block_count(hp.Structures(3, 3, 3, table=(0, -10, -10, -23))) == 262656
     assert hp.hp_canonical_block_count(hp.Structures(3, 3, 3, table=(0, -25, -25, -57))) == 0
+
+
+def test_low10_pair_list_is_every_odd_pair():
+    # the wide block geometry's pair list (shared by host tables and kernel)
+    src = open(os.path.join(ROOT, "paper_2008_05612_amd", "csrc", "hp_internal.h")).read()
+    words = [int(re.search(r"kLow10Pairs%d = (0x[0-9a-f]+)ull" % i, src).group(1), 16)
+             for i in (0, 1)]
+    n = int(re.search(r"kLow10NumPairs = (\d+);", src).group(1))
+    got = [((words[p // 8] >> (8 * (p % 8))) & 15, ((words[p // 8] >> (8 * (p % 8))) >> 4) & 15)
+           for p in range(16)]
+    want = [(a, b) for a in range(10) for b in range(a + 1, 10) if (b - a) >= 3 and (b - a) % 2]
+    assert n == 16 and sorted(got) == want and len(set(got)) == 16
+    # 1 block row, 10 weights, 16 pair rows and 2 index rows fit the 32 rows
+    assert 1 + 10 + n + 2 <= 32
+
+
+def test_mid10_odd_pair_list_is_every_odd_pair():
+    # canonical wide blocks of odd N: x-indices 0 .. 4 sit at offsets 0 .. 4,
+    # 5 .. 9 at offsets 6 .. 10 (the middle monomer stays outer)
+    src = open(os.path.join(ROOT, "paper_2008_05612_amd", "csrc", "hp_internal.h")).read()
+    words = [int(re.search(r"kMid10OddPairs%d = (0x[0-9a-f]+)ull" % i, src).group(1), 16)
+             for i in (0, 1)]
+    got = [((words[p // 8] >> (8 * (p % 8))) & 15, ((words[p // 8] >> (8 * (p % 8))) >> 4) & 15)
+           for p in range(16)]
+    off = [x + (x >= 5) for x in range(10)]
+    want = [(a, b) for a in range(10) for b in range(a + 1, 10)
+            if off[b] - off[a] >= 3 and (off[b] - off[a]) % 2]
+    assert sorted(got) == want and len(set(got)) == 16
+
+
+def test_wide_block_count(lib):
+    # wide blocks vary the 10 monomers around the middle; reversal maps block
+    # (a, m, b) -> (rev b, m, rev a): count a <= rev(b) by brute force and
+    # check that the blocks and their reverses cover 2^N sequences once
+    for dims in [(2, 5, 1), (3, 4, 1), (2, 2, 3), (4, 4, 1), (3, 5, 1), (2, 2, 4), (2, 3, 3)]:
+        s = hp.Structures(*dims)
+        N = s.N
+        odd = N & 1
+        h = (N - 10 - odd) // 2
+        rev = lambda x: int(format(x, "0%db" % h)[::-1], 2) if h else 0  # noqa: E731
+        canon = diag = 0
+        for m in range(2 if odd else 1):
+            for a in range(1 << h):
+                for b in range(1 << h):
+                    if a <= rev(b):
+                        canon += 1
+                        diag += a == rev(b)
+        assert hp.hp_wide_block_count(s) == canon, dims
+        assert 1024 * (2 * (canon - diag) + diag) == 1 << N
+    assert hp.hp_wide_block_count(hp.Structures(3, 3, 3)) == 65792
+    assert hp.hp_wide_block_count(hp.Structures(6, 6, 1)) == 33558528
+    assert hp.hp_wide_block_count(hp.Structures(3, 3, 1)) == 0          # N < 10
+    assert hp.hp_wide_block_count(hp.Structures(3, 3, 3, table=(0, -10, -10, -23))) == 0
+    fake_ws = ctypes.c_void_p(256)
+    s = hp.Structures(4, 4, 1)
+    assert lib.hp_enumerate_symmetric_wide(s.handle, fake_ws, 5, 5, None, None, None, None,
+                                           None) == -1
+    assert lib.hp_enumerate_symmetric_wide(s.handle, fake_ws, 0, 137, None, None, None, None,
+                                           None) == -1
+    assert lib.hp_enumerate_symmetric_wide(s.handle, None, 0, 1, None, None, None, None,
+                                           None) == -1
+    t = hp.Structures(3, 3, 3, table=(0, -10, -10, -23))
+    assert lib.hp_enumerate_symmetric_wide(t.handle, fake_ws, 0, 1, None, None, None, None,
+                                           None) == -5
 
 
 def test_low8_pair_list_is_every_odd_pair():

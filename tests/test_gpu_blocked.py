@@ -116,7 +116,7 @@ def test_blocked_pair_table_weight_three(dims, lo, hi):
 
 
 @pytest.mark.parametrize("nw,mode", [(2, 0), (4, 0), (8, 0), (2, 1), (4, 1), (8, 1), (2, 2), (4, 2),
-                                     (8, 2)])
+                                     (8, 2), (4, 3)])
 def test_blocked_every_launch_shape(nw, mode):
     keep = hp.hp_blocked_selected()
     try:
@@ -245,8 +245,69 @@ def test_autotune_blocked_selects_a_shape_and_keeps_results():
         s = hp.Structures(5, 5, 1)
         (nw, mode), ms = hp.hp_autotune_blocked(s, s.workspace(), 0, 1 << 18, repeats=1)
         assert (nw, mode) == hp.hp_blocked_selected()
-        assert nw in (2, 4, 8) and mode in (0, 1, 2) and len(ms) == 9 and min(ms) > 0
-        assert ms[[2, 4, 8].index(nw) * 3 + mode] == min(ms)
+        assert len(ms) == 10 and min(ms) > 0       # wide blocks apply to 5x5
+        assert (nw, mode) in [(2, 0), (2, 1), (2, 2), (4, 0), (4, 1), (4, 2), (8, 0), (8, 1),
+                              (8, 2), (4, 3)]
+        assert ms[9 if mode == 3 else [2, 4, 8].index(nw) * 3 + mode] == min(ms)
         _assert_equal(run((5, 5, 1), BLK, 777, 777 + 5000), _oracle((5, 5, 1), 777, 777 + 5000))
     finally:
         hp.hp_blocked_select(*keep)
+
+
+# ---------------------------------------------------------------------------
+# wide blocks (staging mode 3): 1024 sequences per workgroup, first product
+# shared by the waves
+# ---------------------------------------------------------------------------
+
+@pytest.fixture()
+def wide():
+    keep = hp.hp_blocked_selected()
+    hp.hp_blocked_select(4, 3)
+    yield
+    hp.hp_blocked_select(*keep)
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 1), (4, 4, 1), (3, 5, 1), (2, 3, 3), (2, 2, 4)])
+def test_wide_full_small_lattices(wide, dims):
+    N = dims[0] * dims[1] * dims[2]
+    _assert_equal(run(dims, BLK, 0, 1 << N), _oracle(dims, 0, 1 << N))
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 1), (3, 1000), (1023, 1025), (1000, 3100), (40000, 65536),
+                                   (1, 65535), (1024, 2048), (64512, 65536)])
+def test_wide_ragged_ranges_4x4(wide, lo, hi):
+    _assert_equal(run((4, 4, 1), BLK, lo, hi), _oracle((4, 4, 1), lo, hi))
+
+
+@pytest.mark.parametrize("dims,size", [((5, 5, 1), 3001), ((2, 3, 4), 2777), ((3, 3, 3), 2111),
+                                       ((6, 6, 1), 2200)])
+def test_wide_config_lattice_windows(wide, dims, size):
+    N = dims[0] * dims[1] * dims[2]
+    for lo, hi in _windows(N, size, 0x2008056121 + N):
+        _assert_equal(run(dims, BLK, lo, hi), _oracle(dims, lo, hi))
+
+
+@pytest.mark.parametrize("dims,lo,hi,thresholds", [((4, 4, 1), 0, 1 << 16, (1, 2, 3)),
+                                                   ((3, 3, 3), 777, 777 + 3000, (2, 4))])
+def test_wide_gap_threshold(wide, dims, lo, hi, thresholds):
+    import torch
+    s = hp.Structures(*dims)
+    ws = s.workspace()
+    st = oracle.structures(*dims)
+    for th in thresholds:
+        o = torch.full((hi - lo,), -7, dtype=torch.int16, device="cuda")
+        g = torch.zeros(hi - lo, dtype=torch.uint8, device="cuda")
+        hp.hp_enumerate_gap(s, ws, BLK, lo, hi, th, o, None, g)
+        torch.cuda.synchronize()
+        gs = oracle.ground_states_gap(st, np.arange(lo, hi, dtype=np.uint64), threshold=th)
+        assert np.array_equal(o.cpu().numpy().view(np.uint16), gs.out), th
+        assert np.array_equal(g.cpu().numpy(), gs.gap), th
+
+
+@pytest.mark.parametrize("dims", [(5, 5, 1), (2, 3, 4)])
+def test_wide_full_map_equals_popcount(wide, dims):
+    import torch
+    o2, d2, n2 = _full_map_invariants(dims, BLK)
+    o0, d0, n0 = _full_map_invariants(dims, hp.FORM_POPCOUNT)
+    assert torch.equal(o0, o2)
+    assert np.array_equal(d0, d2) and n0 == n2

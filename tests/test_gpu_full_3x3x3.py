@@ -1,5 +1,6 @@
 """The full pure-HP 3x3x3 map (all 2^27 sequences x 103346 conformations) in
-all three kernel forms, against the CPU oracle's full map.
+all three kernel forms (the blocked form in its per-wave and its wide
+launch shapes), against the CPU oracle's full map.
 
 The oracle's map is a committed fixture (tests/golden/pure_hp_3x3x3_map.txt,
 written by tests/golden/make_pure_hp_3x3x3.py from the oracle alone): SHA-256
@@ -17,8 +18,9 @@ from tests import _golden333 as g333
 from tests.conftest import gpu_available
 
 pytestmark = pytest.mark.gpu
-FORMS = {"blocked_i8": hp.FORM_BLOCKED_I8, "gemm_i8": hp.FORM_GEMM_I8,
-         "popcount": hp.FORM_POPCOUNT}
+# form and, for the blocked form, its launch shape (waves, staging mode)
+FORMS = {"blocked_i8": (hp.FORM_BLOCKED_I8, (4, 2)), "blocked_i8_wide": (hp.FORM_BLOCKED_I8, (4, 3)),
+         "gemm_i8": (hp.FORM_GEMM_I8, None), "popcount": (hp.FORM_POPCOUNT, None)}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -34,14 +36,20 @@ def full_maps():
     ws = s.workspace()
     total = 1 << 27
     res = {}
-    for name, form in FORMS.items():
-        out = torch.full((total,), -2, dtype=torch.int16, device="cuda")
-        d = torch.zeros(s.n_class, dtype=torch.int64, device="cuda")
-        nd = torch.zeros(1, dtype=torch.int64, device="cuda")
-        print("3x3x3 full map, form", name, flush=True)
-        hp.hp_enumerate(s, ws, form, 0, total, out, None, d, nd)
-        torch.cuda.synchronize()
-        res[name] = (out, d.cpu().numpy().view(np.uint64), int(nd.item()))
+    keep = hp.hp_blocked_selected()
+    try:
+        for name, (form, shape) in FORMS.items():
+            if shape:
+                hp.hp_blocked_select(*shape)
+            out = torch.full((total,), -2, dtype=torch.int16, device="cuda")
+            d = torch.zeros(s.n_class, dtype=torch.int64, device="cuda")
+            nd = torch.zeros(1, dtype=torch.int64, device="cuda")
+            print("3x3x3 full map, form", name, flush=True)
+            hp.hp_enumerate(s, ws, form, 0, total, out, None, d, nd)
+            torch.cuda.synchronize()
+            res[name] = (out, d.cpu().numpy().view(np.uint64), int(nd.item()))
+    finally:
+        hp.hp_blocked_select(*keep)
     return s, res, g333.canonical_sequences()
 
 
@@ -68,7 +76,7 @@ def test_three_forms_agree(full_maps):
     s, res, canon = full_maps
     ref = res["blocked_i8"]
     assert not bool((ref[0] == -2).any())
-    for name in ("gemm_i8", "popcount"):
+    for name in ("blocked_i8_wide", "gemm_i8", "popcount"):
         assert torch.equal(res[name][0], ref[0]), name
         assert np.array_equal(res[name][1], ref[1]), name
         assert res[name][2] == ref[2], name

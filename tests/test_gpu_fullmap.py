@@ -1,8 +1,9 @@
 """Full-map driver: checkpoint/resume, and the full 6x6 map.
 
 The 6x6 map (2^36 sequences x 57337 conformations, 137 GB resident; the
-blocked form over reversal-canonical blocks, in steps of 2^25 blocks, so that
-every step crosses the library's own cuts at 2^22 blocks).  Its parity
+blocked form over reversal-canonical wide blocks, in steps of 2^33
+sequences, so that every step crosses the library's own launch cuts at 2^30
+sequences).  Its parity
 checks: every entry written and the sum invariant over all 2^36 sequences,
 the symmetry invariant on a large random sample, oracle windows at both ends
 and at seeded offsets, the oracle on the blocks on both sides of launch
@@ -16,7 +17,8 @@ import pytest
 import oracle
 import paper_2008_05612_amd as hp
 from paper_2008_05612_amd import fullmap
-from tests._canon import canonical_block_sequences, reverse_bits
+from tests._canon import (canonical_block_sequences, canonical_wide_block_sequences,
+                          reverse_bits)
 from tests.conftest import gpu_available
 
 pytestmark = pytest.mark.gpu
@@ -108,9 +110,13 @@ def test_full_6x6_map():
     for lo in offs:
         gs = oracle.ground_states(st, lo, lo + 4096)
         assert np.array_equal(out[lo:lo + 4096].cpu().numpy().view(np.uint16), gs.out), lo
-    # the blocks on both sides of launch cuts (2^22 canonical blocks per launch)
-    for t in (1 << 22) - 1, 1 << 22, (5 << 22) - 1, 5 << 22:
-        seqs, diag = canonical_block_sequences(N, t)
+    # the blocks on both sides of launch cuts (2^30 sequences per launch:
+    # 2^20 wide blocks or 2^22 blocks of 256)
+    wide = res["geometry"] == "wide"
+    cut = 1 << (20 if wide else 22)
+    block_seqs = canonical_wide_block_sequences if wide else canonical_block_sequences
+    for t in cut - 1, cut, 5 * cut - 1, 5 * cut:
+        seqs, diag = block_seqs(N, t)
         gs = oracle.ground_states_gap(st, seqs, threshold=1)
         idx = torch.from_numpy(seqs.view(np.int64)).cuda()
         ridx = torch.from_numpy(reverse_bits(seqs, N).view(np.int64)).cuda()

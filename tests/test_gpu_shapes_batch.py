@@ -107,16 +107,25 @@ def _batch_jobs(batch=None):
     return jobs, bufs
 
 
-@pytest.mark.parametrize("form", [hp.FORM_GEMM_I8, hp.FORM_BLOCKED_I8])
-def test_batch_matches_oracle(form):
+# blocked batches run wide blocks by default (every job here has N >= 10);
+# with a per-wave staging mode selected they run blocks of 256
+@pytest.mark.parametrize("form,shape", [(hp.FORM_GEMM_I8, None), (hp.FORM_BLOCKED_I8, None),
+                                        (hp.FORM_BLOCKED_I8, (4, 2))])
+def test_batch_matches_oracle(form, shape):
     import torch
     batch = BATCH if form == hp.FORM_GEMM_I8 else BATCH_BLOCKED
-    jobs, bufs = _batch_jobs(batch)
-    bws = torch.zeros(hp._binding.batch_workspace_bytes(len(jobs)), dtype=torch.uint8,
-                      device="cuda")
-    print("batch of", len(jobs), "form", form, flush=True)
-    hp.hp_enumerate_batch(jobs, form, bws)
-    torch.cuda.synchronize()
+    keep = hp.hp_blocked_selected()
+    try:
+        if shape:
+            hp.hp_blocked_select(*shape)
+        jobs, bufs = _batch_jobs(batch)
+        bws = torch.zeros(hp._binding.batch_workspace_bytes(len(jobs)), dtype=torch.uint8,
+                          device="cuda")
+        print("batch of", len(jobs), "form", form, "shape", shape, flush=True)
+        hp.hp_enumerate_batch(jobs, form, bws)
+        torch.cuda.synchronize()
+    finally:
+        hp.hp_blocked_select(*keep)
     for (dims, lo, hi), b in zip(batch, bufs):
         _check(_host(*b), oracle.ground_states(oracle.structures(*dims), lo, hi))
 

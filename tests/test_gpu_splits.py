@@ -3,7 +3,8 @@
 hp_enumerate, hp_enumerate_gap and hp_sample cut a range into launches of
 2^30 indices counted from the range's start, offsetting every per-index
 output; hp_enumerate_symmetric_blocked cuts a canonical-block range into
-launches of 2^22 blocks.  Each test hands the library ONE range that crosses
+launches of 2^22 blocks, hp_enumerate_symmetric_wide a wide-block range into
+launches of 2^20 blocks.  Each test hands the library ONE range that crosses
 such a cut (not 256-aligned, so the blocked form also meets ragged blocks on
 both sides of it) and checks oracle windows at the start, on both sides of
 the cut and at the end, plus the count invariant over the whole range.
@@ -13,7 +14,7 @@ import pytest
 
 import oracle
 import paper_2008_05612_amd as hp
-from tests._canon import canonical_block_sequences
+from tests._canon import canonical_block_sequences, canonical_wide_block_sequences
 from tests.conftest import gpu_available
 
 pytestmark = pytest.mark.gpu
@@ -136,6 +137,43 @@ def test_symmetric_blocked_across_the_launch_cut(six):
     d3 = torch.zeros_like(d1)
     nd3 = torch.zeros_like(nd1)
     hp.hp_enumerate_symmetric_blocked(s, ws, cut - 1, cut + 1, None, None, d3, nd3)
+    torch.cuda.synchronize()
+    assert np.array_equal(d3.cpu().numpy().view(np.uint64), want)
+    assert int(nd3.item()) == want_nd
+
+
+def test_symmetric_wide_across_the_launch_cut(six):
+    """Canonical wide blocks [B, B + 2^20 + 300) in one call (cut at
+    B + 2^20) against calls of 2^19 blocks; the two wide blocks at the cut
+    against the oracle (counts only, as above)."""
+    import torch
+    s, ws, st = six
+    cut_n = 1 << 20
+    b_lo = 4321
+    b_hi = b_lo + cut_n + 300
+    cut = b_lo + cut_n
+    d1 = torch.zeros(s.n_class, dtype=torch.int64, device="cuda")
+    nd1 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    print("6x6 canonical wide blocks [%d, %d) in one call" % (b_lo, b_hi), flush=True)
+    hp.hp_enumerate_symmetric_wide(s, ws, b_lo, b_hi, None, None, d1, nd1)
+    d2 = torch.zeros_like(d1)
+    nd2 = torch.zeros_like(nd1)
+    for b in range(b_lo, b_hi, cut_n // 2):
+        hp.hp_enumerate_symmetric_wide(s, ws, b, min(b + cut_n // 2, b_hi), None, None, d2, nd2)
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2) and torch.equal(nd1, nd2)
+    want = np.zeros(s.n_class, dtype=np.uint64)
+    want_nd = 0
+    for t in (cut - 1, cut):
+        seqs, diag = canonical_wide_block_sequences(36, t)
+        gs = oracle.ground_states_gap(st, seqs, threshold=1)
+        w = 1 if diag else 2
+        want += np.bincount(gs.out[gs.out != oracle.NONE], minlength=s.n_class).astype(
+            np.uint64) * np.uint64(w)
+        want_nd += int((gs.out == oracle.NONE).sum()) * w
+    d3 = torch.zeros_like(d1)
+    nd3 = torch.zeros_like(nd1)
+    hp.hp_enumerate_symmetric_wide(s, ws, cut - 1, cut + 1, None, None, d3, nd3)
     torch.cuda.synchronize()
     assert np.array_equal(d3.cpu().numpy().view(np.uint64), want)
     assert int(nd3.item()) == want_nd
