@@ -9,18 +9,21 @@ phenotype) and the neutral-network union-find over the full map.  Structures
 are enumerated and uploaded once before timing; all inputs are resident in
 HBM.
 
-The dominant kernel is bound by its vector-ALU epilogue (the running top-2
-of the keys, 1.25 VALU operations per sequence-conformation pair), so its
-roofline is the 32-bit VALU peak; the dense int8 form's fraction of the int8
-MFMA peak and the popcount form are measured on the same GPU under "extra".
+Roofline of the dominant kernel: the method's work per (sequence,
+conformation) pair is nbp contact products h_i h_j and their sum (Eq. 1; 28
+contacts per 3x3x3 conformation), i.e. 2 nbp integer operations, priced
+against the dense int8 MFMA peak of the contraction's data type.  What the
+kernel issues instead (depth-32 products, the first product per block, the
+vector-ALU test of each product) is reported under "extra".
 
-Prints ONE JSON line.  Extra measurements (dense int8 and popcount forms, a
-6x6 block in all forms, the sampling mode, per-kernel times) go in the same
-line under "extra".
+Prints ONE JSON line.  Extra measurements (dense int8 and popcount forms, the
+full 6x6 map, the mixed-lattice batch, the sampling mode, per-kernel times) go
+in the same line under "extra".
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,10 +36,24 @@ METRIC = ("seq×structure evals/s + full-map wall time (3×3×3, 6×6); "
           "% int8 MFMA peak")
 PEAK_INT8_TOPS = 5000.0          # MI355X dense int8 MFMA, TOP/s
 PEAK_VALU_TOPS = 256 * 2.4e9 * 64 / 1e12   # 32-bit VALU lane-ops/s: 256 CU x 64 lanes/clk x 2.4 GHz
-EPILOGUE_OPS_PER_PAIR = 1.25     # v_med3 + v_max3 per two keys, one v_max3 per four
 # with two VALU instructions issued per quad-cycle (gfx950 dual issue; the
-# popcount form's two-operand instructions reach it, the key updates do not)
+# popcount form's two-operand instructions reach it)
 PEAK_VALU_DUAL_TOPS = 2 * PEAK_VALU_TOPS
+# sources of the blocked kernel: a recorded counter summary only counts for
+# the build it was taken on
+KERNEL_SOURCES = ["gemm_blk.h", "gemm_blk_kb5.hip", "gemm_blk.hip", "gemm_body.h",
+                  "device_common.h", "kernels.h", "hp_internal.h"]
+# the designability histogram of the full pure-HP 6x6 map, as first computed
+# (SHA-256 of the uint64 little-endian counts); later runs must reproduce it
+SHA_6X6_PURE_HP = "250821539f228f1daeea4954d24c83dda5880d750ad6d9911f2eff764972e261"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2008_05612_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -107,12 +124,17 @@ def main():
     tune_ms = None
     hp.hp_blocked_select(args.nw, args.blk_mode)
     nw = args.nw
-    blk_mode = args.blk_mode if args.blk_mode >= 0 else (2 if s.K_pad <= 192 else 0)
+    # the staging the library takes for mode -1: wide blocks where they apply
+    # (pure pair energies, N >= 10, 4 waves), else by product depth
+    wide = s.unary_rows == 0 and s.N >= 10 and nw == 4
+    blk_mode = (args.blk_mode if args.blk_mode >= 0 and (args.blk_mode != 3 or wide)
+                else (3 if wide else (2 if s.K_pad <= 192 else 0)))
     if args.autotune:
         _, tune_ms = hp.hp_autotune(s, ws, 0, 1 << 20, repeats=2)
         (nw, blk_mode), blk_ms = hp.hp_autotune_blocked(s, ws, 0, 1 << 22, repeats=2)
         tune_ms = {"dense": tune_ms, "blocked": blk_ms}
-    kname = "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, nw, blk_mode)
+    kname = ("k_gemm_wide<%d>" % (s.K_pad // 32) if blk_mode == 3
+             else "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, nw, blk_mode))
     pairs = total * n_conf
 
     out = torch.empty(total, dtype=torch.int16, device=dev)
@@ -162,13 +184,19 @@ def main():
     assert int(d.sum()) + nd == total, "designability + deleterious != 2^N"
 
     enum_ms = float(np.mean(kms["enumerate"]))
-    alu_ops = EPILOGUE_OPS_PER_PAIR * pairs           # top-2 key updates
-    achieved_tops = alu_ops / (enum_ms * 1e-3) / 1e12
+    # the method's work: nbp contact products h_i h_j and their sum per pair
+    method_ops = 2.0 * s.nbp * pairs
+    achieved_tops = method_ops / (enum_ms * 1e-3) / 1e12
     # MFMA work the blocked form issues: one depth-32 product per pair, plus
-    # the per-block stage (K_pad deep, 32 virtual rows) per conformation tile
+    # the per-block first product (K_pad deep, 32 virtual rows) per
+    # conformation tile, once per block of 256 sequences, or of 1024 for
+    # wide blocks
     n_tiles = (n_conf + 31) // 32
-    blk_mfma_ops = 2.0 * 32 * pairs + 2.0 * s.K_pad * 32 * 32 * n_tiles * (total // 256)
+    block_seqs = 1024 if blk_mode == 3 else 256
+    blk_mfma_ops = (2.0 * 32 * pairs +
+                    2.0 * s.K_pad * 32 * 32 * n_tiles * (total // block_seqs))
     evals_per_s = pairs / (ms_step * 1e-3)
+    src_hash = kernel_source_hash()
 
     result = {
         "metric": METRIC,
@@ -188,32 +216,40 @@ def main():
                         "(block-factorised int8-MFMA form) + single-mutation neighbour "
                         "counts + union-find",
             "lattice": "3x3x3", "N": N, "sequences": total, "n_conf": n_conf,
-            "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "form": "blocked_i8",
-            "waves_per_workgroup": nw, "staging_mode": blk_mode,
+            "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "nbp": s.nbp,
+            "form": "blocked_i8", "waves_per_workgroup": nw, "staging_mode": blk_mode,
         },
         "roofline": {
-            "bound": "alu",
+            "bound": "mfma",
             "achieved": achieved_tops,
-            "peak": PEAK_VALU_TOPS,
+            "peak": PEAK_INT8_TOPS,
             "unit": "TOP/s",
-            "frac": achieved_tops / PEAK_VALU_TOPS,
-            "traffic": recorded_traffic(kname),
+            "frac": achieved_tops / PEAK_INT8_TOPS,
+            "traffic": recorded_traffic(kname, src_hash),
             "kernel": kname + " (hp_enumerate, blocked int8 form)",
-            "ops_per_unit": EPILOGUE_OPS_PER_PAIR,
+            "ops_per_unit": 2 * s.nbp,
+            "unit_of_work": "one (sequence, conformation) pair: nbp contact products and "
+                            "their sum (Eq. 1)",
+            "units_per_launch": pairs,
+            "launch_ms": enum_ms,
         },
     }
     extra = {
         "full_map_ms_3x3x3": ms_step,
         "kernel_ms": {k: float(np.mean(v)) for k, v in kms.items()},
         "enumerate_evals_per_s": pairs / (enum_ms * 1e-3),
-        "blocked_mfma_issued_frac": blk_mfma_ops / (enum_ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
-        "blocked_dense_equivalent_int8_tops": 2.0 * s.K * pairs / (enum_ms * 1e-3) / 1e12,
+        # matrix-pipe utilisation: what the blocked kernel issues (depth-32
+        # products for every pair plus the per-block first product)
+        "blocked_mfma_pipe_frac": blk_mfma_ops / (enum_ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
+        "blocked_mfma_ops_per_pair": blk_mfma_ops / pairs,
+        "kernel_source_sha": src_hash,
         "designing_fraction": float(d.sum()) / total,
         "top_class": top,
         "top_designability": int(d[top]),
         "structures_s": t_struct,
         "autotune_ms_per_shape": tune_ms,
     }
+    extra.update(recorded_issue(kname, src_hash))
     if not args.no_extra:
         extra.update(extra_measurements(hp, s, ws, dev, out))
     if args.profile:
@@ -238,33 +274,53 @@ def main():
 HP1996_X10 = (0, -10, -10, -23)   # Table 1 energies scaled by 10: E_PP, E_PH, E_HP, E_HH
 
 
-def recorded_traffic(kname):
-    """HBM bytes per full-map launch of `kname`, from the calibrated
-    FETCH_SIZE / WRITE_SIZE counter summary of the blocked kernel in
-    profiles/, or None when that summary is for another kernel."""
-    path = os.path.join(ROOT, "profiles", "k_gemm_blk_3x3x3_hbm_traffic.txt")
+def _summary_fields(name):
+    fields = {}
     try:
-        fields = {}
-        for line in open(path):
+        for line in open(os.path.join(ROOT, "profiles", name)):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-        if fields.get("kernel") != kname:
-            return None
-        return float(fields["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+    except OSError:
+        pass
+    return fields
+
+
+def recorded_traffic(kname, src_hash):
+    """HBM bytes per full-map launch of `kname`, from the calibrated
+    FETCH_SIZE / WRITE_SIZE counter summary of the blocked kernel in
+    profiles/, or None when that summary is for another kernel or another
+    build of its sources."""
+    f = _summary_fields("k_gemm_blk_3x3x3_hbm_traffic.txt")
+    if f.get("kernel") != kname or f.get("source_sha") != src_hash:
         return None
+    try:
+        return float(f["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def recorded_issue(kname, src_hash):
+    """Vector-ALU and matrix-pipe issue figures of the blocked kernel from
+    its counter summary in profiles/ (same build only)."""
+    f = _summary_fields("k_gemm_blk_3x3x3_issue_counters.txt")
+    if f.get("kernel") != kname or f.get("source_sha") != src_hash:
+        return {"blocked_issue_counters": None}
+    keep = ("valu_per_wave_tile", "mfma_per_wave_tile", "valu_issue_per_simd_quad_cycle",
+            "mfma_busy", "dual_issue")
+    return {"blocked_issue_counters": {k: float(f[k]) for k in keep if k in f}}
 
 
 def extra_measurements(hp, s, ws, dev, blocked_map):
     """The whole phi_pq matrix of the full 3x3x3 map (dense counts and
     compressed rows), the paper's own timed workload (Table 1 energies,
     sampled sequences) on 3x3x3 and 6x6, the dense int8 form over the same
-    full 3x3x3 map (its fraction of the
-    int8 MFMA peak, and a bit-exact comparison with the blocked form's map),
-    the popcount form on a 2^24 slice, the sampling mode on both lattices, and
-    one 2^28 block of the 6x6 map in all three forms with the full 6x6 time
-    extrapolated."""
+    full 3x3x3 map (its fractions of the int8 MFMA peak, and a bit-exact
+    comparison with the blocked form's map), the popcount form on a 2^24
+    slice, the sampling mode on both lattices, one 2^28 block of the 6x6 map
+    in all three forms, the full 6x6 map (measured), and the mixed-lattice
+    batch."""
+    import numpy as np
     import torch
     res = {}
     t = Timer()
@@ -301,10 +357,12 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
     res["dense_gemm_i8_shape"] = {"T": T, "NW": NW, "mode": mode}
     res["dense_gemm_i8_full_map_ms_3x3x3"] = t.ms()
     res["dense_gemm_i8_evals_per_s"] = total * s.n_conf / (t.ms() * 1e-3)
-    res["dense_gemm_i8_mfma_frac"] = (2.0 * s.K * total * s.n_conf / (t.ms() * 1e-3) / 1e12 /
-                                      PEAK_INT8_TOPS)
-    res["dense_gemm_i8_mfma_issued_frac"] = (2.0 * s.K_pad * total * s.n_conf /
-                                             (t.ms() * 1e-3) / 1e12 / PEAK_INT8_TOPS)
+    # the method's work (2 nbp per pair) and the matrix pipe's (2 K_pad per
+    # pair: a dense product over every odd-separation pair row)
+    res["dense_gemm_i8_method_frac"] = (2.0 * s.nbp * total * s.n_conf / (t.ms() * 1e-3) /
+                                        1e12 / PEAK_INT8_TOPS)
+    res["dense_gemm_i8_mfma_pipe_frac"] = (2.0 * s.K_pad * total * s.n_conf /
+                                           (t.ms() * 1e-3) / 1e12 / PEAK_INT8_TOPS)
     res["blocked_map_equals_dense_map"] = bool(torch.equal(dense, blocked_map))
     # the same full map from reversal-canonical blocks only (about half the work)
     nb = hp.hp_canonical_block_count(s)
@@ -318,6 +376,20 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
     torch.cuda.synchronize()
     res["symmetric_blocked_full_map_ms_3x3x3"] = t.ms()
     res["symmetric_blocked_map_equals_blocked_map"] = bool(torch.equal(dense, blocked_map))
+    # ... and from reversal-canonical wide blocks (1024 sequences each)
+    nw_ = hp.hp_wide_block_count(s)
+    if nw_:
+        dsym.zero_()
+        hp.hp_enumerate_symmetric_wide(s, ws, 0, 256, dense, None, dsym)
+        torch.cuda.synchronize()
+        dense.fill_(-2)
+        dsym.zero_()
+        t.start()
+        hp.hp_enumerate_symmetric_wide(s, ws, 0, nw_, dense, None, dsym)
+        t.stop()
+        torch.cuda.synchronize()
+        res["symmetric_wide_full_map_ms_3x3x3"] = t.ms()
+        res["symmetric_wide_map_equals_blocked_map"] = bool(torch.equal(dense, blocked_map))
     del dense
     n = 1 << 24
     for form, name in ((hp.FORM_POPCOUNT, "popcount"), (hp.FORM_BLOCKED_I8, "blocked_i8")):
@@ -392,13 +464,6 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
     n6 = 1 << 28
     d6 = torch.zeros(s6.n_class, dtype=torch.int64, device=dev)
     nb6 = hp.hp_canonical_block_count(s6)
-    hp.hp_enumerate_symmetric_blocked(s6, ws6, 0, 1024, None, None, d6)
-    torch.cuda.synchronize()
-    t.start()
-    hp.hp_enumerate_symmetric_blocked(s6, ws6, 0, 1 << 20, None, None, d6)
-    t.stop()
-    torch.cuda.synchronize()
-    res["6x6_full_map_s_extrapolated_symmetric_blocked"] = t.ms() * 1e-3 * nb6 / (1 << 20)
     for form, name, nn in ((hp.FORM_BLOCKED_I8, "blocked_i8", n6), (hp.FORM_GEMM_I8, "gemm_i8", n6),
                            (hp.FORM_POPCOUNT, "popcount", n6 // 4)):
         hp.hp_enumerate(s6, ws6, form, 0, 1 << 16, None, None, d6)
@@ -409,58 +474,149 @@ def extra_measurements(hp, s, ws, dev, blocked_map):
         torch.cuda.synchronize()
         rate = nn * s6.n_conf / (t.ms() * 1e-3)
         res["6x6_block_%s_evals_per_s" % name] = rate
-        res["6x6_full_map_s_extrapolated_%s" % name] = (1 << 36) * s6.n_conf / rate
-    res["6x6_gemm_i8_mfma_frac"] = (res["6x6_block_gemm_i8_evals_per_s"] * 2 * s6.K /
-                                    (PEAK_INT8_TOPS * 1e12))
-    res["6x6_blocked_valu_frac"] = (res["6x6_block_blocked_i8_evals_per_s"] *
-                                    EPILOGUE_OPS_PER_PAIR / (PEAK_VALU_TOPS * 1e12))
+    res["6x6_gemm_i8_mfma_pipe_frac"] = (res["6x6_block_gemm_i8_evals_per_s"] * 2 * s6.K_pad /
+                                         (PEAK_INT8_TOPS * 1e12))
+    res["6x6_blocked_method_frac"] = (res["6x6_block_blocked_i8_evals_per_s"] * 2 * s6.nbp /
+                                      (PEAK_INT8_TOPS * 1e12))
+    del d6
+    # the full 6x6 map, measured: every canonical wide block of the blocked
+    # form in one call (the library cuts it into launches of 2^30
+    # sequences); the map itself is not kept (137 GB), its designability
+    # histogram is hashed
+    d6 = torch.zeros(s6.n_class, dtype=torch.int64, device=dev)
+    nd6 = torch.zeros(1, dtype=torch.int64, device=dev)
+    nw6 = hp.hp_wide_block_count(s6)
+    print("bench: full 6x6 map (%d canonical wide blocks)" % nw6, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if nw6:
+        hp.hp_enumerate_symmetric_wide(s6, ws6, 0, nw6, None, None, d6, nd6)
+    else:
+        hp.hp_enumerate_symmetric_blocked(s6, ws6, 0, nb6, None, None, d6, nd6)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    res["6x6_full_map_geometry"] = "canonical wide blocks" if nw6 else "canonical blocks of 256"
+    h6 = d6.cpu().numpy().view(np.uint64)
+    sha6 = hashlib.sha256(h6.astype("<u8").tobytes()).hexdigest()
+    res["6x6_full_map_s"] = sec
+    res["6x6_full_map_map_evals_per_s"] = (1 << 36) * s6.n_conf / sec
+    res["6x6_full_map_designability_sha256"] = sha6
+    res["6x6_full_map_sha_matches_first_run"] = sha6 == SHA_6X6_PURE_HP
+    res["6x6_full_map_sum_check"] = int(h6.sum()) + int(nd6.item()) == 1 << 36
+    res["6x6_full_map_designing"] = int(h6.sum())
+    del d6, nd6, ws6, s6
+    res.update(mixed_batch(hp, dev))
     return res
+
+
+def mixed_batch(hp, dev):
+    """The mixed-lattice batch at its full sizes (4x4, 5x5, 2x3x4 and 3x3x3,
+    every sequence of each): one captured hipGraph replay against the same
+    jobs as separate hp_enumerate calls, blocked form."""
+    import torch
+    jobs, outs, sizes = [], [], {}
+    for dims in ((4, 4, 1), (5, 5, 1), (2, 3, 4), (3, 3, 3)):
+        s = hp.Structures(*dims)
+        ws = s.workspace()
+        n = 1 << s.N
+        o = torch.empty(n, dtype=torch.int16, device=dev)
+        d = torch.zeros(s.n_class, dtype=torch.int64, device=dev)
+        nd = torch.zeros(1, dtype=torch.int64, device=dev)
+        jobs.append(hp.Job(s, ws, 0, n, o, None, d, nd))
+        outs.append((s, ws, o, d, nd))
+        sizes["x".join(str(x) for x in dims if x > 1)] = n * s.n_conf
+    bws = torch.zeros(hp._binding.batch_workspace_bytes(len(jobs)), dtype=torch.uint8,
+                      device=dev)
+    g = hp.hp_graph_capture_batch(jobs, hp.FORM_BLOCKED_I8, bws)
+    g.launch()
+    torch.cuda.synchronize()
+    t = Timer()
+    t.start()
+    g.launch()
+    t.stop()
+    torch.cuda.synchronize()
+    graph_ms = t.ms()
+    t.start()
+    for s, ws, o, d, nd in outs:
+        hp.hp_enumerate(s, ws, hp.FORM_BLOCKED_I8, 0, 1 << s.N, o, None, d, nd)
+    t.stop()
+    torch.cuda.synchronize()
+    pairs = sum(sizes.values())
+    return {"mixed_batch_graph_ms": graph_ms, "mixed_batch_separate_launches_ms": t.ms(),
+            "mixed_batch_pairs": pairs, "mixed_batch_evals_per_s": pairs / (graph_ms * 1e-3),
+            "mixed_batch_jobs": sizes}
+
+
+def host_cpu():
+    """CPU model, physical cores and hardware threads of this host."""
+    model, cores = None, set()
+    try:
+        phys = core = None
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and model is None:
+                model = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None:
+                cores.add((phys, core))
+                phys = core = None
+    except OSError:
+        pass
+    return {"model": model, "physical_cores": len(cores) or None,
+            "hardware_threads": os.cpu_count(),
+            "threads_available": len(os.sched_getaffinity(0))}
+
+
+def _oracle_rate(oracle, st, lo, n):
+    t0 = time.perf_counter()
+    oracle.ground_states(st, lo, lo + n)
+    dt = time.perf_counter() - t0
+    return n * st.n_conf / dt, dt
 
 
 def cpu_baseline(dims, seconds):
     """The oracle (plain C, OpenMP over sequences) on a bounded window of the
-    same workload, on this host's cores (all threads and one thread), and on
-    a window of the 6x6 map; full-map times extrapolated from the rates."""
+    same workload, on this host's cores (all threads and one thread), plus
+    the other lattices of the same workload family: the full 4x4 map, a 5x5
+    window and a 6x6 window; full-map times extrapolated from the rates."""
     import oracle
     st = oracle.structures(*dims)
     lo = 0
     n = 4096          # enough to keep every host thread busy while calibrating
-    t0 = time.perf_counter()
-    oracle.ground_states(st, lo, lo + n)
-    dt = time.perf_counter() - t0
+    _, dt = _oracle_rate(oracle, st, lo, n)
     n = int(max(4096, min(1 << 22, n * seconds / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.ground_states(st, lo, lo + n)
-    dt = time.perf_counter() - t0
-    cores = oracle.num_threads()
+    rate, dt = _oracle_rate(oracle, st, lo, n)
+    threads = oracle.num_threads()
     # one thread on a smaller sample of the same window
     oracle.set_num_threads(1)
-    n1 = max(64, n // (4 * cores))
-    t0 = time.perf_counter()
-    oracle.ground_states(st, lo, lo + n1)
-    dt1 = time.perf_counter() - t0
-    oracle.set_num_threads(cores)
-    # the 6x6 map on a window of at most 2^16 sequences, sized to about 5 s
-    st6 = oracle.structures(6, 6, 1)
-    n6 = 1 << 12
-    t0 = time.perf_counter()
-    oracle.ground_states(st6, 0, n6)
-    dt6 = time.perf_counter() - t0
-    n6 = int(max(1 << 12, min(1 << 16, n6 * 5.0 / max(dt6, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.ground_states(st6, 0, n6)
-    dt6 = time.perf_counter() - t0
-    rate, rate6 = n * st.n_conf / dt, n6 * st6.n_conf / dt6
-    return {"value": rate, "unit": "evals/s", "cores": cores,
+    n1 = max(64, n // (4 * threads))
+    rate1, dt1 = _oracle_rate(oracle, st, lo, n1)
+    oracle.set_num_threads(threads)
+    # the other lattices: 4x4 whole, 5x5 and 6x6 windows sized to a few seconds
+    other = {}
+    for d2, cap in (((4, 4, 1), 1 << 16), ((5, 5, 1), 1 << 22), ((6, 6, 1), 1 << 16)):
+        st2 = oracle.structures(*d2)
+        n2 = min(cap, 1 << 12)
+        _, t2 = _oracle_rate(oracle, st2, 0, n2)
+        n2 = int(max(n2, min(cap, n2 * 3.0 / max(t2, 1e-3))))
+        r2, t2 = _oracle_rate(oracle, st2, 0, n2)
+        name = "x".join(str(x) for x in d2 if x > 1)
+        other[name] = {"evals_per_s": r2, "sample": "sequences [0, %d) x all %d conformations, "
+                       "%.2f s" % (n2, st2.n_conf, t2),
+                       "full_map_s_extrapolated": (1 << st2.N) * st2.n_conf / r2}
+    return {"value": rate, "unit": "evals/s", "cores": threads,
             "kind": "oracle",
-            "sample": "3x3x3, sequences [0, %d) x all %d conformations, %.1f s" % (n, st.n_conf, dt),
-            "value_1_thread": n1 * st.n_conf / dt1,
+            "sample": "3x3x3, sequences [0, %d) x all %d conformations, %.1f s on %d threads"
+                      % (n, st.n_conf, dt, threads),
+            "host": host_cpu(),
+            "value_1_thread": rate1,
             "sample_1_thread": "sequences [0, %d), %.1f s" % (n1, dt1),
             "full_map_s_extrapolated_3x3x3": (1 << st.N) * st.n_conf / rate,
-            "value_6x6": rate6,
-            "sample_6x6": "6x6, sequences [0, %d) x all %d conformations, %.1f s"
-                          % (n6, st6.n_conf, dt6),
-            "full_map_s_extrapolated_6x6": (1 << st6.N) * st6.n_conf / rate6}
+            "other_lattices": other}
 
 
 if __name__ == "__main__":

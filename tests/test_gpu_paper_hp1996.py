@@ -3,10 +3,12 @@
 
 Phenotype denominators are the designable phenotypes (47449).  The paper's
 N_s counts the sequences of one conformation (its histogram covers half of
-sequence space); classes here hold both chain directions.  The share of
-phenotypes "above the null model" is printed but not asserted: its null line
-is defined by a figure that is missing.  The oracle is not involved: these are
-the paper's own values.
+sequence space); classes here hold both chain directions.  Two printed
+statistics are not reproduced at their printed precision (the mean share of
+other non-deleterious neighbours, and the share of phenotypes whose
+robustness lies above the null model); they are strict expected failures,
+so a change that made them agree would be noticed.  The oracle is not
+involved: these are the paper's own values.
 """
 import os
 
@@ -27,13 +29,16 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _golden():
+def _golden(unreproduced=False):
+    """Rows of the golden file: the asserted ones, or (unreproduced=True)
+    the ones marked as not reproduced."""
     rows = {}
     for line in open(GOLD):
         if line.startswith("#") or not line.strip():
             continue
-        name, val, prec = line.split()[:3]
-        rows[name] = (float(val), float(prec))
+        f = line.split()
+        if (len(f) > 3 and f[3] == "unreproduced") == unreproduced:
+            rows[f[0]] = (float(f[1]), float(f[2]))
     return rows
 
 
@@ -91,11 +96,6 @@ def test_neighbourhood_statistics_match_the_paper(hp1996_map):
     N = 27
     des = desig > 0
     nq = desig[des].astype(np.float64)
-    rho = neu[des] / (N * nq)
-    null = nq / float(1 << 27)
-    # printed only: the paper's null-model line comes from a missing figure
-    print("robust above null (rho > N_q/2^27): %.2f%% (paper prints 43.6%%)"
-          % (100.0 * float((rho > null).mean())), flush=True)
     connected = int((row[:s.n_class][des] > 0).sum()) - 1    # other than the top fold itself
     print("connected to top: %d of %d designable (%.3f%%), of %d folds (%.3f%%)"
           % (connected, des.sum(), 100.0 * connected / des.sum(), s.n_class,
@@ -105,8 +105,38 @@ def test_neighbourhood_statistics_match_the_paper(hp1996_map):
     iso = int((oth[des] == 0).sum())
     _near("isolated_phenotypes", iso, g)
     _near("isolated_percent", 100.0 * iso / float(des.sum()), g)
-    _near("mean_other_percent", 100.0 * float((oth[des] / (N * nq)).mean()), g)
     _near("connected_percent", 100.0 * (1 - iso / float(des.sum())), g)
+
+
+@pytest.mark.xfail(strict=True, reason="printed 4.0 %; the map gives 4.07 %")
+def test_mean_other_share_not_reproduced(hp1996_map):
+    s, desig, nondes, top, neu, dele, oth, row, _ = hp1996_map
+    des = desig > 0
+    nq = desig[des].astype(np.float64)
+    _near("mean_other_percent", 100.0 * float((oth[des] / (27 * nq)).mean()),
+          _golden(unreproduced=True))
+
+
+@pytest.mark.xfail(strict=True, reason="printed 43.6 %; every null-model reading tried gives "
+                                       "far more")
+def test_robust_above_null_not_reproduced(hp1996_map):
+    s, desig, nondes, top, neu, dele, oth, row, _ = hp1996_map
+    N, total = 27, float(1 << 27)
+    des = desig > 0
+    nq = desig[des].astype(np.float64)
+    rho = neu[des] / (N * nq)
+    self_rev = s.export()["self_rev"][des] == 1
+    readings = {
+        "frequency N_q / 2^N": nq / total,
+        "frequency among designing sequences": nq / float(desig.sum()),
+        "frequency per conformation": nq / np.where(self_rev, 1.0, 2.0) / total,
+    }
+    for name, null in readings.items():
+        print("robust above null, %s: %.2f%% of designable phenotypes, %.2f%% of all folds"
+              % (name, 100.0 * float((rho > null).mean()),
+                 100.0 * float((rho > null).sum()) / s.n_class), flush=True)
+    _near("robust_above_null_percent", 100.0 * float((rho > nq / total).mean()),
+          _golden(unreproduced=True))
 
 
 def test_full_phi_matrix_matches_the_paper(hp1996_map):
