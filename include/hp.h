@@ -438,6 +438,9 @@ hp_status hp_autotune(const hp_structs *s, const void *d_ws, uint64_t seq_lo, ui
  * mutants of phi_q-genotypes, i.e. the numerators of phi_{p,phi_q}.
  * Counters are uint64 arrays of n_class (n_class + 1 for the row); any may
  * be NULL.  Errors: HP_EINVAL for NULL map or phi_q >= n_class.
+ * A 16-byte aligned d_map with N >= 3 is read eight genotypes per lane (one
+ * 16-byte load per mutant bit); any other map one genotype per lane.  The
+ * results are the same; the same holds for hp_phi_counts and hp_components.
  */
 hp_status hp_neighbors(const hp_structs *s, const uint16_t *d_map, uint64_t *d_neutral,
                        uint64_t *d_deleterious, uint64_t *d_other, int32_t phi_q,

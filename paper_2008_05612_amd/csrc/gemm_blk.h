@@ -620,6 +620,11 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
 #pragma unroll
     for (int t = 0; t < kBlkTiles; ++t)
         sf[t] = S2[t * 64 + lane];
+    // Wait for these loads here (s_waitcnt vmcnt(0)): the compiler's wait
+    // counts are the same for every pass of the tile loop, so loads of the
+    // second operand still counted as in flight there would make each pass
+    // also wait for the contact-tile loads issued one group ahead.
+    __builtin_amdgcn_s_waitcnt(0x0f70);
 
     int gb[kBlkTiles], gs[kBlkTiles], thr[kBlkTiles];
 #pragma unroll

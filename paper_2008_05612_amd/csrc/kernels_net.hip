@@ -58,13 +58,109 @@ __global__ __launch_bounds__(256) void k_neighbors(const uint16_t *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Eight genotypes per lane.  The map is read as 16-byte vectors holding the
+// genotypes 8k .. 8k+7: the mutants of bits 0..2 lie in the same vector, and
+// the mutants of bit i >= 3 of all eight are the eight entries of vector
+// k ^ 2^(i-3).  One 16-byte load then replaces eight 2-byte loads, so a wave
+// issues an eighth of the load instructions.  These kernels serve 16-byte
+// aligned maps with N >= 3; the one-genotype kernels cover the rest.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t geno8(const uint4 &v, int r)
+{
+    const uint32_t w = r < 2 ? v.x : (r < 4 ? v.y : (r < 6 ? v.z : v.w));
+    return (w >> (16 * (r & 1))) & 0xffffu;
+}
+
+__device__ __forceinline__ void unpack8(const uint4 &v, uint32_t q[8])
+{
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        q[r] = geno8(v, r);
+}
+
+static bool use_geno8(const uint16_t *map, int N)
+{
+    return N >= 3 && (reinterpret_cast<uintptr_t>(map) & 15u) == 0;
+}
+
+__global__ __launch_bounds__(256) void k_neighbors8(const uint4 *__restrict__ m4, int N, uint64_t n8,
+                                                    int n_class, unsigned long long *neutral,
+                                                    unsigned long long *deleterious,
+                                                    unsigned long long *other, int phi_q,
+                                                    unsigned long long *phi_row)
+{
+    const uint16_t *__restrict__ map = reinterpret_cast<const uint16_t *>(m4);
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n8;
+         k += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t q[8];
+        unpack8(m4[k], q);
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            any |= int(q[r]) < n_class;   // 0xFFFF and ids beyond n_class are not phenotypes
+        if (!any)
+            continue;
+        // a: neutral mutants, d: deleterious ones; the other N - a - d change the phenotype
+        uint32_t a[8], d[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            a[r] = d[r] = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const uint32_t p = q[r ^ (1 << i)];
+                a[r] += p == q[r] ? 1u : 0u;
+                d[r] += p == HP_NONE ? 1u : 0u;
+            }
+        for (int i = 3; i < N; ++i) {
+            const uint4 nv = m4[k ^ (uint64_t(1) << (i - 3))];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const uint32_t p = geno8(nv, r);
+                a[r] += p == q[r] ? 1u : 0u;
+                d[r] += p == HP_NONE ? 1u : 0u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (int(q[r]) >= n_class)
+                continue;
+            const uint32_t o = uint32_t(N) - a[r] - d[r];
+            if (neutral && a[r])
+                atomicAdd(&neutral[q[r]], (unsigned long long)a[r]);
+            if (deleterious && d[r])
+                atomicAdd(&deleterious[q[r]], (unsigned long long)d[r]);
+            if (other && o)
+                atomicAdd(&other[q[r]], (unsigned long long)o);
+            if (phi_row && int(q[r]) == phi_q) {
+                const uint64_t g = 8 * k + uint64_t(r);
+                for (int i = 0; i < N; ++i) {
+                    const uint16_t p = map[g ^ (uint64_t(1) << i)];
+                    atomicAdd(&phi_row[(p == HP_NONE || int(p) >= n_class) ? n_class : int(p)],
+                              1ull);
+                }
+            }
+        }
+    }
+}
+
 hipError_t launch_neighbors(const uint16_t *map, int N, int n_class, unsigned long long *neutral,
                             unsigned long long *deleterious, unsigned long long *other, int phi_q,
                             unsigned long long *phi_row, hipStream_t st)
 {
     const uint64_t total = uint64_t(1) << N;
-    hipLaunchKernelGGL(k_neighbors, dim3(grid_for(total, 256)), dim3(256), 0, st, map, N, total,
-                       n_class, neutral, deleterious, other, phi_q, phi_row);
+    if (use_geno8(map, N)) {
+        const uint64_t n8 = total / 8;
+        hipLaunchKernelGGL(k_neighbors8, dim3(grid_for(n8, 256)), dim3(256), 0, st,
+                           reinterpret_cast<const uint4 *>(map), N, n8, n_class, neutral,
+                           deleterious, other, phi_q, phi_row);
+    } else {
+        hipLaunchKernelGGL(k_neighbors, dim3(grid_for(total, 256)), dim3(256), 0, st, map, N,
+                           total, n_class, neutral, deleterious, other, phi_q, phi_row);
+    }
     return hipGetLastError();
 }
 
@@ -101,6 +197,62 @@ __global__ __launch_bounds__(256) void k_phi_counts(const uint16_t *__restrict__
             atomicAdd(&row[q], (unsigned long long)neutral);
         if (del)
             atomicAdd(&row[n_class], (unsigned long long)del);
+    }
+}
+
+// Eight genotypes per lane (the vector layout of k_neighbors8).
+__global__ __launch_bounds__(256) void k_phi_counts8(const uint4 *__restrict__ m4, int N,
+                                                     uint64_t n8, int n_class,
+                                                     unsigned long long *counts)
+{
+    const uint64_t ld = uint64_t(n_class) + 1;
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n8;
+         k += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t q[8];
+        unpack8(m4[k], q);
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            any |= int(q[r]) < n_class;
+        if (!any)
+            continue;
+        uint32_t neutral[8], del[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            neutral[r] = del[r] = 0;
+        // one mutant p of genotype r: neutral and deleterious ones are
+        // counted in registers, one into another phenotype adds at (q, p)
+        auto take = [&](int r, uint32_t p) {
+            if (int(q[r]) >= n_class)
+                return;
+            if (p == q[r])
+                ++neutral[r];
+            else if (int(p) >= n_class)
+                ++del[r];
+            else
+                atomicAdd(&counts[uint64_t(q[r]) * ld + p], 1ull);
+        };
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                take(r, q[r ^ (1 << i)]);
+        for (int i = 3; i < N; ++i) {
+            const uint4 nv = m4[k ^ (uint64_t(1) << (i - 3))];
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                take(r, geno8(nv, r));
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (int(q[r]) >= n_class)
+                continue;
+            unsigned long long *row = counts + uint64_t(q[r]) * ld;
+            if (neutral[r])
+                atomicAdd(&row[q[r]], (unsigned long long)neutral[r]);
+            if (del[r])
+                atomicAdd(&row[n_class], (unsigned long long)del[r]);
+        }
     }
 }
 
@@ -222,8 +374,14 @@ hipError_t launch_phi_counts(const uint16_t *map, int N, int n_class, unsigned l
                              hipStream_t st)
 {
     const uint64_t total = uint64_t(1) << N;
-    hipLaunchKernelGGL(k_phi_counts, dim3(grid_for(total, 256)), dim3(256), 0, st, map, N, total,
-                       n_class, counts);
+    if (use_geno8(map, N)) {
+        const uint64_t n8 = total / 8;
+        hipLaunchKernelGGL(k_phi_counts8, dim3(grid_for(n8, 256)), dim3(256), 0, st,
+                           reinterpret_cast<const uint4 *>(map), N, n8, n_class, counts);
+    } else {
+        hipLaunchKernelGGL(k_phi_counts, dim3(grid_for(total, 256)), dim3(256), 0, st, map, N,
+                           total, n_class, counts);
+    }
     return hipGetLastError();
 }
 
@@ -310,6 +468,42 @@ __global__ __launch_bounds__(256) void k_uf_hook(const uint16_t *__restrict__ ma
     }
 }
 
+// Eight genotypes per lane (the vector layout of k_neighbors8): the edges
+// g -- g|bit of the genotypes 8k .. 8k+7.
+__global__ __launch_bounds__(256) void k_uf_hook8(const uint4 *__restrict__ m4, int N,
+                                                  uint32_t *parent, uint64_t n8)
+{
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n8;
+         k += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t q[8];
+        unpack8(m4[k], q);
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            any |= q[r] != HP_NONE;
+        if (!any)
+            continue;
+        const uint32_t g0 = uint32_t(8 * k);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (!(r & (1 << i)) && q[r] != HP_NONE && q[r | (1 << i)] == q[r])
+                    uf_unite(parent, g0 + r, g0 + (r | (1 << i)));
+        for (int i = 3; i < N; ++i) {
+            const uint64_t u = k | (uint64_t(1) << (i - 3));
+            if (u == k)
+                continue;
+            const uint4 nv = m4[u];
+            const uint32_t u0 = uint32_t(8 * u);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (q[r] != HP_NONE && geno8(nv, r) == q[r])
+                    uf_unite(parent, g0 + r, u0 + r);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_uf_compress(const uint16_t *__restrict__ map,
                                                      uint32_t *parent, uint32_t *compsize,
                                                      uint64_t total)
@@ -355,7 +549,11 @@ hipError_t launch_components(const uint16_t *map, int N, uint32_t *labels, uint3
     if (largest && (e = launch_fill_u32(largest, 0u, uint64_t(n_class), st)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_uf_init, grid, block, 0, st, map, labels, compsize, total);
-    hipLaunchKernelGGL(k_uf_hook, grid, block, 0, st, map, N, labels, total);
+    if (use_geno8(map, N))
+        hipLaunchKernelGGL(k_uf_hook8, dim3(grid_for(total / 8, 256)), block, 0, st,
+                           reinterpret_cast<const uint4 *>(map), N, labels, total / 8);
+    else
+        hipLaunchKernelGGL(k_uf_hook, grid, block, 0, st, map, N, labels, total);
     hipLaunchKernelGGL(k_uf_compress, grid, block, 0, st, map, labels, compsize, total);
     hipLaunchKernelGGL(k_uf_count, grid, block, 0, st, map, labels, compsize, ncomp, largest,
                        n_class, total);

@@ -101,3 +101,44 @@ def test_network_3x3x3_full_invariants():
     assert np.all(labels[des] <= np.arange(1 << 27, dtype=np.uint32)[des])
     assert np.all(o[labels[des]] == o[des])
     assert np.all(labels[~des] == 0xFFFFFFFF)
+
+
+@pytest.mark.parametrize("dims,none_frac,extra,offset", [
+    ((4, 4, 1), 0.3, 2, 0), ((4, 4, 1), 0.3, 2, 1), ((2, 3, 3), 0.6, 0, 0),
+    ((2, 3, 3), 0.6, 0, 3), ((4, 5, 1), 0.1, 1, 0), ((4, 5, 1), 0.1, 1, 5)])
+def test_network_synthetic_maps_both_layouts(dims, none_frac, extra, offset):
+    """Seeded synthetic maps (few distinct ids so that neutral networks are
+    large, deleterious genotypes, ids at or beyond n_class that are not
+    phenotypes) read from a 16-byte aligned buffer (eight genotypes per lane)
+    and from a buffer offset by `offset` genotypes (one genotype per lane):
+    neighbour counts, phi row, phi matrix and component labels all equal the
+    oracle's."""
+    import torch
+    s = hp.Structures(*dims)
+    n = 1 << s.N
+    rng = np.random.default_rng(7919 * s.N + 13 * offset + int(10 * none_frac))
+    ids = rng.integers(0, s.n_class, 12)
+    phen = ids[rng.integers(0, 12, n)].astype(np.uint16)
+    if extra:
+        sel = rng.random(n) < 0.03
+        phen[sel] = (s.n_class + rng.integers(0, extra, int(sel.sum()))).astype(np.uint16)
+    phen[rng.random(n) < none_frac] = NONE
+    buf = torch.zeros(n + 16, dtype=torch.int16, device="cuda")
+    view = buf[offset:offset + n]
+    view.copy_(torch.from_numpy(phen.view(np.int16)))
+    assert (view.data_ptr() % 16 == 0) == (offset % 8 == 0)
+    top = int(ids[0])
+    neu, dele, oth, row, labels, size, ncomp, largest = _gpu_network(s, view, top)
+    nb = oracle.neighbors(s.N, phen, s.n_class, phi_q=top)
+    assert np.array_equal(neu, nb.neutral)
+    assert np.array_equal(dele, nb.deleterious)
+    assert np.array_equal(oth, nb.other)
+    assert np.array_equal(row, nb.phi_row)
+    lab = oracle.components(s.N, phen)
+    assert np.array_equal(labels, lab)
+    des = phen != NONE
+    assert np.array_equal(size, np.bincount(lab[des], minlength=n).astype(np.uint32))
+    c = torch.zeros((s.n_class, s.n_class + 1), dtype=torch.int64, device="cuda")
+    hp.hp_phi_counts(s, view, c)
+    torch.cuda.synchronize()
+    assert np.array_equal(c.cpu().numpy().view(np.uint64), oracle.phi_counts(s.N, phen, s.n_class))
