@@ -704,18 +704,21 @@ void or_ground_states_brute(int X, int Y, int Z, const uint8_t *class_keys, long
 /* Single-point-mutation neighbourhood (Eq. 2) and neutral networks.         */
 /* ------------------------------------------------------------------------ */
 
-/* For every designing genotype g (phenotype q = map[g]) and every one of its
- * N one-bit mutants p = map[g ^ (1<<i)]:
+/* For every designing genotype g (phenotype q = map[g] < n_class) and every
+ * one of its N one-bit mutants p = map[g ^ (1<<i)]:
  *   neutral[q]++ if p == q; deleterious[q]++ if p is 0xFFFF; other[q]++ else.
- * If phi_q >= 0, phi_row[p] (p < n_class) or phi_row[n_class] (deleterious)
- * counts the mutants of phi_q-genotypes.  All counters are += .            */
+ * If phi_q >= 0, phi_row[p] (p < n_class) or phi_row[n_class] (deleterious:
+ * 0xFFFF, or an id that is not a phenotype) counts the mutants of
+ * phi_q-genotypes.  Ids at or beyond n_class are not phenotypes (Eq. 2 sums
+ * over the genotypes of a phenotype), so such genotypes have no counters, as
+ * in or_phi_counts.  All counters are += .                                  */
 void or_neighbors(int N, const uint16_t *map, long n_class, uint64_t *neutral,
                   uint64_t *deleterious, uint64_t *other, int phi_q, uint64_t *phi_row)
 {
     uint64_t total = (uint64_t)1 << N;
     for (uint64_t g = 0; g < total; g++) {
         uint16_t q = map[g];
-        if (q == OR_NONE)
+        if (q == OR_NONE || (long)q >= n_class)
             continue;
         for (int i = 0; i < N; i++) {
             uint16_t p = map[g ^ ((uint64_t)1 << i)];
@@ -726,7 +729,7 @@ void or_neighbors(int N, const uint16_t *map, long n_class, uint64_t *neutral,
             else
                 other[q]++;
             if (phi_q >= 0 && q == (uint16_t)phi_q)
-                phi_row[p == OR_NONE ? n_class : (long)p]++;
+                phi_row[(p == OR_NONE || (long)p >= n_class) ? n_class : (long)p]++;
         }
     }
 }

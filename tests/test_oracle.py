@@ -318,6 +318,40 @@ def test_neighbors_match_python(dims):
     assert int(row[top]) == int(nb.neutral[top])
 
 
+def test_neighbors_ids_beyond_n_class():
+    """Ids at or beyond n_class are not phenotypes: such genotypes have no
+    counters, and as mutants they count as 'other' in the three counters and
+    in the deleterious column of the phi row (like 0xFFFF), the column the
+    phi matrix uses for them.  Brute force with plain loops on a 2^10 map."""
+    N, n_class = 10, 6
+    rng = np.random.default_rng(5)
+    phen = rng.integers(0, n_class + 3, 1 << N).astype(np.uint16)
+    phen[rng.random(1 << N) < 0.2] = NONE
+    q0 = int(phen[phen < n_class][0])
+    neu = np.zeros(n_class, np.uint64); dele = np.zeros_like(neu); oth = np.zeros_like(neu)
+    row = np.zeros(n_class + 1, np.uint64)
+    for g in range(1 << N):
+        q = int(phen[g])
+        if q >= n_class:          # 0xFFFF included
+            continue
+        for i in range(N):
+            p = int(phen[g ^ (1 << i)])
+            if p == q:
+                neu[q] += 1
+            elif p == NONE:
+                dele[q] += 1
+            else:
+                oth[q] += 1
+            if q == q0:
+                row[n_class if p >= n_class else p] += 1
+    nb = oracle.neighbors(N, phen, n_class, phi_q=q0)
+    assert np.array_equal(nb.neutral, neu)
+    assert np.array_equal(nb.deleterious, dele)
+    assert np.array_equal(nb.other, oth)
+    assert np.array_equal(nb.phi_row, row)
+    assert np.array_equal(oracle.phi_counts(N, phen, n_class)[q0], row)
+
+
 def _py_components(N, phen):
     lab = [0xFFFFFFFF] * (1 << N)
     for g in range(1 << N):
