@@ -286,12 +286,19 @@ def _summary_fields(name):
     return fields
 
 
+def _summary_name(kname, what):
+    """profiles/ file of the counter summary `what` for kernel `kname`
+    (k_gemm_wide<KB> or k_gemm_blk<KB,NW,MODE>) on the 3x3x3 map."""
+    family = "k_gemm_wide" if kname.startswith("k_gemm_wide") else "k_gemm_blk"
+    return "%s_3x3x3_%s.txt" % (family, what)
+
+
 def recorded_traffic(kname, src_hash):
     """HBM bytes per full-map launch of `kname`, from the calibrated
     FETCH_SIZE / WRITE_SIZE counter summary of the blocked kernel in
     profiles/, or None when that summary is for another kernel or another
     build of its sources."""
-    f = _summary_fields("k_gemm_blk_3x3x3_hbm_traffic.txt")
+    f = _summary_fields(_summary_name(kname, "hbm_traffic"))
     if f.get("kernel") != kname or f.get("source_sha") != src_hash:
         return None
     try:
@@ -303,7 +310,7 @@ def recorded_traffic(kname, src_hash):
 def recorded_issue(kname, src_hash):
     """Vector-ALU and matrix-pipe issue figures of the blocked kernel from
     its counter summary in profiles/ (same build only)."""
-    f = _summary_fields("k_gemm_blk_3x3x3_issue_counters.txt")
+    f = _summary_fields(_summary_name(kname, "issue_counters"))
     if f.get("kernel") != kname or f.get("source_sha") != src_hash:
         return {"blocked_issue_counters": None}
     keep = ("valu_per_wave_tile", "mfma_per_wave_tile", "valu_issue_per_simd_quad_cycle",

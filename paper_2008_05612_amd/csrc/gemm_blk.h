@@ -294,6 +294,39 @@ __device__ __forceinline__ void stage_two(const v4i &a2, const v4i (&sf)[S2_LDS 
     }
 }
 
+// Stage two of one conformation tile in the wide kernel: as stage_two, with
+// two changes that free registers for a third accumulator (four waves per
+// SIMD still fit): the running top-2 of each lane lives in LDS (g[t * 64],
+// read and written only by the rare key update), and the product of
+// sequence tile t + 2 is issued before tile t's test, so each test reads a
+// product issued a full test earlier.
+__device__ __forceinline__ void stage_two_wide(const v4i &a2, const v4i (&sf)[kBlkTiles], int2 *g,
+                                               int (&thr)[kBlkTiles], int conf_base,
+                                               int win_shift)
+{
+    const v16i zero = {};
+    v16i acc[3];
+    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[0], zero, 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[1], zero, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t) {
+        if (t + 2 < kBlkTiles)
+            acc[(t + 2) % 3] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[t + 2], zero, 0, 0, 0);
+        const v16i &a = acc[t % 3];
+        if (__builtin_expect(__any(max16(a) >= thr[t]), 0)) {
+            int b = 0, sc = 0;
+#pragma unroll
+            for (int r = 0; r < 16; r += 2)
+                top2_add2(b, sc, a[r], a[r + 1]);
+            int2 v = g[t * 64];
+            top2_merge(v.x, v.y, window_to_global(b, conf_base, win_shift),
+                       window_to_global(sc, conf_base, win_shift));
+            g[t * 64] = v;
+            thr[t] = absorb_threshold(v.y, win_shift);
+        }
+    }
+}
+
 // Staging of the C1 tiles:
 //   kBlkLds  : double-buffered LDS, one barrier per tile; stage one of a tile
 //              runs right before its stage two.
@@ -597,7 +630,7 @@ __device__ __forceinline__ uint64_t wide_canonical_outer(const EnumJob &j, uint6
 // vectors, a2s two groups of 4 packed first products.
 template <int KB, bool CANON>
 __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *vlds,
-                                          v4i (*a2s)[4][64])
+                                          v4i (*a2s)[4][64], int2 *gbs)
 {
     bool diag = false;
     const uint64_t outer = CANON ? wide_canonical_outer(j, blk, &diag) : blk << kWideBits;
@@ -626,10 +659,14 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
     // also wait for the contact-tile loads issued one group ahead.
     __builtin_amdgcn_s_waitcnt(0x0f70);
 
-    int gb[kBlkTiles], gs[kBlkTiles], thr[kBlkTiles];
+    // this lane's running top-2 (global keys) per sequence tile, in LDS
+    int2 *const top2 = gbs + wave * (kBlkTiles * 64) + lane;
+    int thr[kBlkTiles];
 #pragma unroll
-    for (int t = 0; t < kBlkTiles; ++t)
-        gb[t] = gs[t] = thr[t] = 0;
+    for (int t = 0; t < kBlkTiles; ++t) {
+        top2[t * 64] = int2{0, 0};
+        thr[t] = 0;
+    }
 
     const int n_tiles = j.n_tiles;
     const int win_tiles = j.blk_win_tiles;
@@ -677,8 +714,7 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
                     conf_base += win_tiles * kTileConf;
                     wnext += win_tiles;
                 }
-                stage_two<false>(a2s[buf][tt][lane], sf, nullptr, lane, gb, gs, thr, conf_base,
-                                 win_shift);
+                stage_two_wide(a2s[buf][tt][lane], sf, top2, thr, conf_base, win_shift);
             }
             if (tt == 0 && nt < n_tiles) {
                 if (!kPrefetch)
@@ -693,6 +729,13 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
         __syncthreads();
     }
 
+    int gb[kBlkTiles], gs[kBlkTiles];
+#pragma unroll
+    for (int t = 0; t < kBlkTiles; ++t) {
+        const int2 v = top2[t * 64];
+        gb[t] = v.x;
+        gs[t] = v.y;
+    }
 #pragma unroll
     for (int t = 0; t < kBlkTiles; ++t) {
         const int ob = __shfl_xor(gb[t], 32);
@@ -719,11 +762,13 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
 template <int KB, bool CANON>
 __global__ __launch_bounds__(256) void k_gemm_wide(EnumJob j)
 {
-    // first-product A operand of the block (the same for all four waves) and
-    // the packed first products of the current and the next group of 4 tiles
+    // first-product A operand of the block (the same for all four waves), the
+    // packed first products of the current and the next group of 4 tiles and
+    // every lane's running top-2 keys
     __shared__ v4i vlds[KB * 64];
     __shared__ v4i a2s[2][4][64];
-    wide_body<KB, CANON>(j, (CANON ? j.lo : j.lo >> kWideBits) + blockIdx.x, vlds, a2s);
+    __shared__ int2 gbs[4 * kBlkTiles * 64];
+    wide_body<KB, CANON>(j, (CANON ? j.lo : j.lo >> kWideBits) + blockIdx.x, vlds, a2s, gbs);
 }
 
 // Batched wide blocks for jobs of one product depth: workgroup b scores the
@@ -733,6 +778,7 @@ __global__ __launch_bounds__(256) void k_gemm_wide_batch(BatchHeader *hdr, int i
 {
     __shared__ v4i vlds[KB * 64];
     __shared__ v4i a2s[2][4][64];
+    __shared__ int2 gbs[4 * kBlkTiles * 64];
     const EnumJob *jobs = reinterpret_cast<const EnumJob *>(hdr + 1);
     const int njobs = hdr->njobs;
     const int64_t *start = reinterpret_cast<const int64_t *>(jobs + njobs);
@@ -747,7 +793,7 @@ __global__ __launch_bounds__(256) void k_gemm_wide_batch(BatchHeader *hdr, int i
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
     const EnumJob &j = jobs[lo];
-    wide_body<KB, false>(j, (j.lo >> kWideBits) + uint64_t(it - start[lo]), vlds, a2s);
+    wide_body<KB, false>(j, (j.lo >> kWideBits) + uint64_t(it - start[lo]), vlds, a2s, gbs);
 }
 
 template <int KB>
