@@ -133,7 +133,11 @@ def main():
         _, tune_ms = hp.hp_autotune(s, ws, 0, 1 << 20, repeats=2)
         (nw, blk_mode), blk_ms = hp.hp_autotune_blocked(s, ws, 0, 1 << 22, repeats=2)
         tune_ms = {"dense": tune_ms, "blocked": blk_ms}
-    kname = ("k_gemm_wide<%d>" % (s.K_pad // 32) if blk_mode == 3
+    # with 16 waves selected, the whole map (one range cut at a multiple of
+    # 2^19) takes wide blocks of 4096 sequences where N >= 19
+    wide12 = blk_mode == 3 and nw == 16 and s.N >= 19
+    kname = ("k_gemm_wide12<%d>" % (s.K_pad // 32) if wide12
+             else "k_gemm_wide<%d>" % (s.K_pad // 32) if blk_mode == 3
              else "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, nw, blk_mode))
     pairs = total * n_conf
 
@@ -189,10 +193,10 @@ def main():
     achieved_tops = method_ops / (enum_ms * 1e-3) / 1e12
     # MFMA work the blocked form issues: one depth-32 product per pair, plus
     # the per-block first product (K_pad deep, 32 virtual rows) per
-    # conformation tile, once per block of 256 sequences, or of 1024 for
-    # wide blocks
+    # conformation tile, once per block of 256 sequences, or of 1024 or 4096
+    # for wide blocks
     n_tiles = (n_conf + 31) // 32
-    block_seqs = 1024 if blk_mode == 3 else 256
+    block_seqs = 4096 if wide12 else 1024 if blk_mode == 3 else 256
     blk_mfma_ops = (2.0 * 32 * pairs +
                     2.0 * s.K_pad * 32 * 32 * n_tiles * (total // block_seqs))
     evals_per_s = pairs / (ms_step * 1e-3)
@@ -288,7 +292,8 @@ def _summary_fields(name):
 
 def _summary_name(kname, what):
     """profiles/ file of the counter summary `what` for kernel `kname`
-    (k_gemm_wide<KB> or k_gemm_blk<KB,NW,MODE>) on the 3x3x3 map."""
+    (k_gemm_wide<KB>, k_gemm_wide12<KB> or k_gemm_blk<KB,NW,MODE>) on the
+    3x3x3 map."""
     family = "k_gemm_wide" if kname.startswith("k_gemm_wide") else "k_gemm_blk"
     return "%s_3x3x3_%s.txt" % (family, what)
 

@@ -362,19 +362,23 @@ hp_status hp_enumerate_batch_static(const hp_job *jobs, int njobs, int form, voi
 /*
  * Launch shape of HP_FORM_BLOCKED_I8: every wave scores one block of 256
  * sequences.  hp_blocked_select sets, process-wide, the waves per workgroup
- * nw (2, 4 or 8; default 4; the waves of a workgroup share each staged
+ * nw (2, 4 or 8, or 16 with mode 3; default 4; the waves of a workgroup share each staged
  * contact tile) and the staging mode (0: double-buffered LDS; 1:
  * triple-buffered LDS with the block-level product of the next tile issued
  * while the current tile's keys are updated; 2: as 0, with the per-sequence
  * operand of the second product read from LDS instead of held in registers;
  * 3: wide blocks, 1024 sequences sharing every monomer above the low 10 per
  * workgroup of 4 waves, one first product per conformation tile shared by
- * the waves -- pure pair energies over plain ranges only, elsewhere mode 3
- * acts as -1; -1, default: 3 where wide blocks apply, else 2 for
- * K_pad <= 192, else 0).  hp_blocked_selected
+ * the waves; with nw = 16, where both ends of the range are multiples of
+ * 2^19 and N >= 19, 4096 sequences (monomers 0 .. 4 and 6, 8, .., 18) per
+ * workgroup of 16 waves (a quarter of the contact-matrix reads, slower on
+ * the full 3x3x3 map) -- pure pair energies over plain ranges only,
+ * elsewhere mode 3 acts as -1; -1, default: 3 where wide blocks apply, else
+ * 2 for K_pad <= 192, else 0).  hp_blocked_selected
  * reports them (either pointer may be NULL).  Results never depend on the
  * shape.
- * Errors: HP_EINVAL for another value, or mode 3 with nw != 4.
+ * Errors: HP_EINVAL for another value, mode 3 with nw other than 4 or 16, or
+ * nw = 16 with another mode.
  */
 hp_status hp_blocked_select(int nw, int mode);
 void hp_blocked_selected(int *nw, int *mode);

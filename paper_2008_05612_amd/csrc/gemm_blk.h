@@ -498,64 +498,90 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk_batch(BatchHeader *hdr, in
 }
 
 // ---------------------------------------------------------------------------
-// Wide blocks: 1024 sequences sharing every monomer above the low 10 (plain
-// ranges, pure pair energies), one per workgroup of 4 waves.  Wave w scores
-// the 256 sequences whose monomers 8 and 9 are the bits of w; the block
-// term, the weights w_v of the 10 varying monomers and their 16 pair terms
-// fill 29 of the 32 virtual rows, so ONE first product per conformation tile
-// serves all four waves: each wave computes it for every fourth tile (one
-// group of 4 tiles ahead) and hands the packed result to the others through
-// LDS.  Per 32 x 32 tile the matrix pipe runs one depth-32 product plus a
-// quarter of the first product's K_pad/32, and the first product is packed
-// once per workgroup instead of once per wave.
+// Wide blocks (pure pair energies): one block of sequences sharing every
+// outer monomer per workgroup, wave w scoring the 256 sequences whose
+// varying monomers above the low 8 are the bits of w.  The block term, the
+// weights w_v of the varying monomers and their 16 pair terms fill all but
+// one or three of the 32 virtual rows, so ONE first product per
+// conformation tile serves every wave of the workgroup: each wave computes
+// it for every NW-th tile (one group of NW tiles ahead) and hands the packed
+// result to the others through LDS.  Three geometries (G):
+//   0  plain ranges, 1024 sequences (the low 10 monomers), 4 waves;
+//   1  reversal-canonical blocks, 1024 sequences (the 10 around the middle),
+//      4 waves;
+//   2  plain ranges cut at multiples of 2^19 when 16 waves are selected,
+//      4096 sequences (monomers 0 .. 4 and the even ones 6 .. 18: equal
+//      parity never touches, so 12 varying monomers still have only 16
+//      pairs), 16 waves, so a first product serves 4096 sequences.
+// Per 32 x 32 tile the matrix pipe runs one depth-32 product plus 1/NW of the
+// first product's K_pad/32, and the first product is packed once per
+// workgroup.
 // ---------------------------------------------------------------------------
 
-constexpr int kWideRowVV = 11, kWideRowIdx = 27;
+template <int G>
+constexpr int wide_bits() { return G == 2 ? kWide12Bits : kWideBits; }
+template <int G>
+constexpr int wide_waves() { return G == 2 ? kWide12Waves : 4; }
+// virtual rows: 0 block term, 1 .. nb weights, then 16 pairs, then 2 index rows
+template <int G>
+constexpr int wide_row_vv() { return 1 + wide_bits<G>(); }
+template <int G>
+constexpr int wide_row_idx() { return wide_row_vv<G>() + 16; }
 
-// Varying monomer x (0 .. 9) of a wide block: the low 10 for plain ranges;
-// for reversal-canonical blocks the 10 around the middle, h = j.half_bits
-// outer monomers on each side (and, for odd N, the middle monomer h + 5
-// outer as well).
-template <bool CANON>
+// Varying monomer x of a wide block: G 0 the low 10; G 1 the 10 around the
+// middle, h = j.half_bits outer monomers on each side (and, for odd N, the
+// middle monomer h + 5 outer as well); G 2 monomers 0 .. 4, 6, 8, .., 18.
+template <int G>
 __device__ __forceinline__ int wide_pos(const EnumJob &j, int x)
 {
-    return CANON ? j.half_bits + x + (x >= 5 ? (j.N & 1) : 0) : x;
+    if constexpr (G == 1)
+        return j.half_bits + x + (x >= 5 ? (j.N & 1) : 0);
+    else if constexpr (G == 2)
+        return x < 5 ? x : 2 * x - 4;
+    else
+        return x;
 }
 
-template <bool CANON>
+template <int G>
 __device__ __forceinline__ bool wide_varies(const EnumJob &j, int i)
 {
-    if (!CANON)
+    if constexpr (G == 0) {
         return i < kWideBits;
-    const int h = j.half_bits, odd = j.N & 1;
-    return i >= h && i < h + kWideBits + odd && !(odd && i == h + 5);
+    } else if constexpr (G == 2) {
+        return i < 5 || (i >= 6 && i <= 18 && !(i & 1));
+    } else {
+        const int h = j.half_bits, odd = j.N & 1;
+        return i >= h && i < h + kWideBits + odd && !(odd && i == h + 5);
+    }
 }
 
 // Pair p (0 .. 15) of the block's varying monomers as x-indices a | b << 4.
-template <bool CANON>
+template <int G>
 __device__ __forceinline__ int wide_pair(const EnumJob &j, int p)
 {
-    const uint64_t w = (CANON && (j.N & 1)) ? (p < 8 ? kMid10OddPairs0 : kMid10OddPairs1)
-                                             : (p < 8 ? kLow10Pairs0 : kLow10Pairs1);
+    const uint64_t w = G == 2                     ? (p < 8 ? kW12Pairs0 : kW12Pairs1)
+                       : (G == 1 && (j.N & 1)) ? (p < 8 ? kMid10OddPairs0 : kMid10OddPairs1)
+                                                 : (p < 8 ? kLow10Pairs0 : kLow10Pairs1);
     return int((w >> (8 * (p & 7))) & 0xffu);
 }
 
 // First-product A operand of a wide block, fragment kb of this lane:
-// virtual row m (0 block term, 1 .. 10 the weight of varying monomer m - 1,
-// 11 .. 26 the varying pairs, 27 and 28 the index rows) over product rows
+// virtual row m (0 block term, 1 .. nb the weight of varying monomer m - 1,
+// then the 16 varying pairs, then the two index rows) over product rows
 // k = 32 kb + 16 half + q of C1.
-template <bool CANON>
+template <int G>
 __device__ __forceinline__ v4i wide_v_fragment(const EnumJob &j, uint64_t outer, int m, int half,
                                                int kb)
 {
+    constexpr int kRowVV = wide_row_vv<G>(), kRowIdx = wide_row_idx<G>();
     const int N = j.N;
     const int coef = j.blk_coef;
-    const int wv = m >= 1 && m < kWideRowVV ? wide_pos<CANON>(j, m - 1) : -1;
+    const int wv = m >= 1 && m < kRowVV ? wide_pos<G>(j, m - 1) : -1;
     int va = -1, vb = -1;
-    if (m >= kWideRowVV && m < kWideRowIdx) {
-        const int pr = wide_pair<CANON>(j, m - kWideRowVV);
-        va = wide_pos<CANON>(j, pr & 15);
-        vb = wide_pos<CANON>(j, pr >> 4);
+    if (m >= kRowVV && m < kRowIdx) {
+        const int pr = wide_pair<G>(j, m - kRowVV);
+        va = wide_pos<G>(j, pr & 15);
+        vb = wide_pos<G>(j, pr >> 4);
     }
     // product row k < K is the pair (i, i + d) of the k-th odd separation
     // d >= 3 in (d, i) order
@@ -574,18 +600,18 @@ __device__ __forceinline__ v4i wide_v_fragment(const EnumJob &j, uint64_t outer,
             const int k = kbase + q4 * 4 + bb;
             int v = 0;
             if (k == j.K) {
-                v = m == kWideRowIdx ? 1 : 0;
+                v = m == kRowIdx ? 1 : 0;
             } else if (k == j.K + 1) {
-                v = m == kWideRowIdx + 1 ? -1 : 0;
+                v = m == kRowIdx + 1 ? -1 : 0;
             } else if (d < N) {
                 const int jj = i + d;
-                const bool out_i = !wide_varies<CANON>(j, i), out_j = !wide_varies<CANON>(j, jj);
+                const bool out_i = !wide_varies<G>(j, i), out_j = !wide_varies<G>(j, jj);
                 const bool h_i = (outer >> i) & 1u, h_j = (outer >> jj) & 1u;
                 if (m == 0)
                     v = out_i && out_j && h_i && h_j ? -coef : 0;
-                else if (m < kWideRowVV)
+                else if (m < kRowVV)
                     v = (i == wv && out_j && h_j) || (jj == wv && out_i && h_i) ? -coef : 0;
-                else if (m < kWideRowIdx)
+                else if (m < kRowIdx)
                     v = i == va && jj == vb ? -coef : 0;
             }
             word |= (uint32_t(v) & 0xffu) << (8 * bb);
@@ -625,31 +651,48 @@ __device__ __forceinline__ uint64_t wide_canonical_outer(const EnumJob &j, uint6
     return (uint64_t(a) << (h + kWideBits + odd)) | (uint64_t(m) << (h + 5)) | b;
 }
 
-// One wide block for the workgroup's four waves: plain block `blk` (the 1024
-// sequences blk * 1024 + x) or canonical block `blk`; vlds holds KB * 64
-// vectors, a2s two groups of 4 packed first products.
-template <int KB, bool CANON>
-__device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *vlds,
-                                          v4i (*a2s)[4][64], int2 *gbs)
+// Plain-12 block index t -> outer bits: chunk t >> 7 of 2^19 sequences, and
+// within it bits 0 .. 6 of t on the outer monomers 5, 7, .., 17.
+__device__ __forceinline__ uint64_t wide12_outer(uint64_t t)
 {
+    uint64_t o = (t >> 7) << kWide12ChunkBits;
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        o |= ((t >> k) & 1u) << (5 + 2 * k);
+    return o;
+}
+
+// The work of one workgroup: wave w of NW = wide_waves<G>() scores the 256
+// sequences x = 256 w + 32 t + col (t = 0 .. 7) of block `blk` (plain 10:
+// sequence >> 10; canonical: canonical block index; plain 12: chunk << 7 |
+// the outer bits of the chunk).  vlds holds the block's first-product
+// fragments, a2s the packed first products of two groups of NW tiles
+// ([2][NW][64]), gbs every lane's running top-2 keys ([NW][8][64]).
+template <int KB, int G>
+__device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *vlds, v4i *a2s,
+                                          int2 *gbs)
+{
+    constexpr int NW = wide_waves<G>();
     bool diag = false;
-    const uint64_t outer = CANON ? wide_canonical_outer(j, blk, &diag) : blk << kWideBits;
+    const uint64_t outer = G == 1   ? wide_canonical_outer(j, blk, &diag)
+                           : G == 2 ? wide12_outer(blk)
+                                    : blk << kWideBits;
     // Contact tiles of the first product are loaded one group ahead into
-    // registers for shallow products; deep ones (K_pad > 192) load right
-    // before use, which keeps four waves per SIMD.
-    constexpr bool kPrefetch = KB <= 6;
+    // registers for shallow products; deep ones (K_pad > 192, or > 160 with
+    // 16 waves) load right before use, which keeps four waves per SIMD.
+    constexpr bool kPrefetch = KB <= (NW == 4 ? 6 : 5);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 31;
     const int half = lane >> 5;
     const v4i *__restrict__ B1 = reinterpret_cast<const v4i *>(j.gemm_b);
 
-    // the four waves build the block's fragments, one kb at a time
-    for (int kb = wave; kb < KB; kb += 4)
-        vlds[kb * 64 + lane] = wide_v_fragment<CANON>(j, outer, col, half, kb);
+    // the waves build the block's fragments, one kb at a time
+    for (int kb = wave; kb < KB; kb += NW)
+        vlds[kb * 64 + lane] = wide_v_fragment<G>(j, outer, col, half, kb);
     v4i sf[kBlkTiles];
     const v4i *__restrict__ S2 = reinterpret_cast<const v4i *>(j.wide_s2) +
-                                 ((CANON ? 4 : 0) + wave) * (kBlkTiles * 64);
+                                 ((G == 0 ? 0 : G == 1 ? 4 : 8) + wave) * (kBlkTiles * 64);
 #pragma unroll
     for (int t = 0; t < kBlkTiles; ++t)
         sf[t] = S2[t * 64 + lane];
@@ -689,7 +732,7 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
             d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(vlds[kb * 64 + lane], c1[kb],
                                                        kb == 0 ? zero : d1, 0, 0, 0);
         }
-        a2s[buf][wave][lane] = pack_d1(d1);
+        a2s[(buf * NW + wave) * 64 + lane] = pack_d1(d1);
     };
 
     v4i c1[KB];
@@ -698,30 +741,31 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
         load_c1(wave, c1);
         first(c1, 0);
     }
-    if (kPrefetch && 4 + wave < n_tiles)
-        load_c1(4 + wave, c1);
+    if (kPrefetch && NW + wave < n_tiles)
+        load_c1(NW + wave, c1);
     __syncthreads();
     int conf_base = 0;
     int wnext = win_tiles;   // first tile of the next key window
-    for (int g = 0; g * 4 < n_tiles; ++g) {
+    for (int g = 0; g * NW < n_tiles; ++g) {
         const int buf = g & 1;
-        const int nt = (g + 1) * 4 + wave;   // this wave's tile of the next group
+        const int nt = (g + 1) * NW + wave;   // this wave's tile of the next group
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            const int tile = g * 4 + tt;
+        for (int tt = 0; tt < NW; ++tt) {
+            const int tile = g * NW + tt;
             if (tile < n_tiles) {
                 if (tile == wnext) {
                     conf_base += win_tiles * kTileConf;
                     wnext += win_tiles;
                 }
-                stage_two_wide(a2s[buf][tt][lane], sf, top2, thr, conf_base, win_shift);
+                stage_two_wide(a2s[(buf * NW + tt) * 64 + lane], sf, top2, thr, conf_base,
+                               win_shift);
             }
             if (tt == 0 && nt < n_tiles) {
                 if (!kPrefetch)
                     load_c1(nt, c1);
                 first(c1, buf ^ 1);
-                if (kPrefetch && nt + 4 < n_tiles)
-                    load_c1(nt + 4, c1);
+                if (kPrefetch && nt + NW < n_tiles)
+                    load_c1(nt + NW, c1);
             }
         }
         // the next group's first products are visible, and this group's
@@ -742,15 +786,22 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
         const int os = __shfl_xor(gs[t], 32);
         top2_merge(gb[t], gs[t], ob, os);
         const int x = wave * 256 + t * 32 + col;
-        if constexpr (CANON) {
+        if constexpr (G == 1) {
             // off the diagonal the block's reverse is never scored: write both;
             // a diagonal block holds each sequence and its reverse itself
             uint64_t sq = outer;
 #pragma unroll
             for (int b = 0; b < kWideBits; ++b)
-                sq |= uint64_t((x >> b) & 1) << wide_pos<true>(j, b);
+                sq |= uint64_t((x >> b) & 1) << wide_pos<1>(j, b);
             const uint64_t rs = diag ? sq : __builtin_bitreverse64(sq) >> (64 - j.N);
             finish_sequence(j, sq, sq, rs, half == 0 && blk < j.hi, gb[t], gs[t], lane == 0, 1);
+        } else if constexpr (G == 2) {
+            uint64_t sq = outer | uint64_t(x & 31);
+#pragma unroll
+            for (int b = 5; b < kWide12Bits; ++b)
+                sq |= uint64_t((x >> b) & 1) << wide_pos<2>(j, b);
+            finish_sequence(j, sq, sq, sq, half == 0 && sq >= j.lo && sq < j.hi, gb[t], gs[t],
+                            lane == 0, 1);
         } else {
             const uint64_t idx = outer + uint64_t(x);
             finish_sequence(j, idx, idx, idx, half == 0 && idx >= j.lo && idx < j.hi, gb[t],
@@ -766,9 +817,21 @@ __global__ __launch_bounds__(256) void k_gemm_wide(EnumJob j)
     // packed first products of the current and the next group of 4 tiles and
     // every lane's running top-2 keys
     __shared__ v4i vlds[KB * 64];
-    __shared__ v4i a2s[2][4][64];
+    __shared__ v4i a2s[2 * 4 * 64];
     __shared__ int2 gbs[4 * kBlkTiles * 64];
-    wide_body<KB, CANON>(j, (CANON ? j.lo : j.lo >> kWideBits) + blockIdx.x, vlds, a2s, gbs);
+    wide_body<KB, CANON ? 1 : 0>(j, (CANON ? j.lo : j.lo >> kWideBits) + blockIdx.x, vlds, a2s,
+                                 gbs);
+}
+
+// Plain ranges cut at multiples of 2^19: blocks of 4096 sequences, 16 waves
+// (one workgroup per CU: 101 KB of LDS at K_pad 160).
+template <int KB>
+__global__ __launch_bounds__(1024) void k_gemm_wide12(EnumJob j)
+{
+    __shared__ v4i vlds[KB * 64];
+    __shared__ v4i a2s[2 * kWide12Waves * 64];
+    __shared__ int2 gbs[kWide12Waves * kBlkTiles * 64];
+    wide_body<KB, 2>(j, ((j.lo >> kWide12ChunkBits) << 7) + blockIdx.x, vlds, a2s, gbs);
 }
 
 // Batched wide blocks for jobs of one product depth: workgroup b scores the
@@ -777,7 +840,7 @@ template <int KB>
 __global__ __launch_bounds__(256) void k_gemm_wide_batch(BatchHeader *hdr, int item_lo)
 {
     __shared__ v4i vlds[KB * 64];
-    __shared__ v4i a2s[2][4][64];
+    __shared__ v4i a2s[2 * 4 * 64];
     __shared__ int2 gbs[4 * kBlkTiles * 64];
     const EnumJob *jobs = reinterpret_cast<const EnumJob *>(hdr + 1);
     const int njobs = hdr->njobs;
@@ -793,7 +856,7 @@ __global__ __launch_bounds__(256) void k_gemm_wide_batch(BatchHeader *hdr, int i
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
     const EnumJob &j = jobs[lo];
-    wide_body<KB, false>(j, (j.lo >> kWideBits) + uint64_t(it - start[lo]), vlds, a2s, gbs);
+    wide_body<KB, 0>(j, (j.lo >> kWideBits) + uint64_t(it - start[lo]), vlds, a2s, gbs);
 }
 
 template <int KB>
@@ -803,12 +866,27 @@ hipError_t launch_wide_batch(BatchHeader *hdr, int item_lo, unsigned grid, hipSt
     return hipGetLastError();
 }
 
+// With 16 waves selected, plain ranges take blocks of 4096 when both ends
+// are multiples of 2^19 and monomer 18 exists; otherwise blocks of 1024
+// (4 waves), the default.  The 4096 geometry re-reads the contact matrix a
+// quarter as often and issues a quarter of the first products, but its one
+// workgroup per CU leaves nothing to run while the 16 waves meet at each
+// group's barrier: measured slower on the full 3x3x3 map.
+inline bool wide12_applies(const EnumJob &j)
+{
+    const uint64_t m = (uint64_t(1) << kWide12ChunkBits) - 1;
+    return j.N >= kWide12ChunkBits && j.hi > j.lo && (j.lo & m) == 0 && (j.hi & m) == 0;
+}
+
 template <int KB>
-hipError_t launch_wide(const EnumJob &j, hipStream_t st)
+hipError_t launch_wide(const EnumJob &j, bool waves16, hipStream_t st)
 {
     if (j.mode == kSeqCanonical) {
         hipLaunchKernelGGL((k_gemm_wide<KB, true>), dim3(unsigned(j.hi - j.lo)), dim3(256), 0, st,
                            j);
+    } else if (waves16 && wide12_applies(j)) {
+        const uint64_t n = ((j.hi - j.lo) >> kWide12ChunkBits) << 7;
+        hipLaunchKernelGGL((k_gemm_wide12<KB>), dim3(unsigned(n)), dim3(1024), 0, st, j);
     } else {
         const uint64_t n = ((j.hi - 1) >> kWideBits) - (j.lo >> kWideBits) + 1;
         hipLaunchKernelGGL((k_gemm_wide<KB, false>), dim3(unsigned(n)), dim3(256), 0, st, j);
@@ -877,7 +955,7 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
     if (j.blk_ngroups > 0 || j.blk_coefB != 0)
         return launch_blk_unary<KB>(j, st);
     if (mode == kBlkStageWide)
-        return launch_wide<KB>(j, st);
+        return launch_wide<KB>(j, nw == 16, st);
     if (mode == kBlkLdsS2) {
         switch (nw) {
         case 2: return launch_blk_shape<KB, 2, kBlkLdsS2>(j, st);
@@ -915,7 +993,7 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
     }                                                                                     \
     hipError_t launch_gemm_wide_kb##KB(const EnumJob &j, hipStream_t st)                  \
     {                                                                                     \
-        return launch_wide<KB>(j, st);                                                    \
+        return launch_wide<KB>(j, false, st);                                             \
     }
 
 }  // namespace hpmap

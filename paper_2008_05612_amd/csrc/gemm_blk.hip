@@ -82,9 +82,11 @@ hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t s
     // where they apply (measured faster at every depth) and otherwise keeps
     // the second operand in LDS for shallow products
     const bool wide_ok = j.wide_s2 && j.mode == kSeqPlain && j.blk_ngroups == 0 &&
-                         j.blk_coefB == 0 && nw == 4;
+                         j.blk_coefB == 0 && (nw == 4 || nw == 16);
     if (mode == kBlkStageWide && !wide_ok)
         mode = -1;
+    if (nw == 16 && mode != kBlkStageWide)
+        nw = 4;   // 16 waves exist only as wide blocks
     if (mode < 0)
         mode = wide_ok ? kBlkStageWide : (j.blk_KB <= 6 ? kBlkStageS2Lds : kBlkStageLds);
     if (j.blk_KB < 1 || j.blk_KB > kDepths)

@@ -35,7 +35,8 @@ struct WsLayout {
     size_t gemm_a = 0;   // int8_t[n_tiles][K_pad/32][64 lanes][16]
     size_t gemm_b = 0;   // blocked form: int8_t[n_tiles][K_pad/32][64 lanes][16], or none
     size_t blk_s2 = 0;   // blocked form: int8_t[2 geometries][8 tiles][64 lanes][16], or none
-    size_t wide_s2 = 0;  // wide blocks: int8_t[2 geometries][4 waves][8 tiles][64 lanes][16], or none
+    size_t wide_s2 = 0;  // wide blocks: int8_t[4 + 4 + 16 waves][8 tiles][64 lanes][16] (geometries:
+                         // plain 10, canonical 10, plain 12), or none
     size_t total = 0;
 };
 
@@ -106,6 +107,19 @@ constexpr int kLow10NumPairs = 16;
 // with odd N (x-indices, same byte layout):
 constexpr uint64_t kMid10OddPairs0 = 0x7151806096854130ull;  // (0,3) (1,4) (5,8) (6,9) (0,6) (0,8) (1,5) (1,7)
 constexpr uint64_t kMid10OddPairs1 = 0x8464937353826291ull;  // (1,9) (2,6) (2,8) (3,5) (3,7) (3,9) (4,6) (4,8)
+// Wide blocks of 4096 sequences for plain ranges, scored by the 16 waves of
+// one workgroup: the 12 varying monomers are 0 .. 4 and the even monomers
+// 6, 8, .., 18 (pos(x) = x for x < 5, 2 x - 4 after).  Monomers of equal
+// parity are never in contact (odd separation), so the only varying pairs
+// are (0,3), (1,4) and those of monomers 1 and 3 with the seven even ones:
+// 16 pairs, and base, 12 weights, 16 pairs and 2 index rows fill 31 of the
+// 32 virtual rows.  The outer monomers 5, 7, .., 17 of a 2^19-sequence
+// chunk index its 128 blocks.  Pairs as x-indices a | b << 4:
+constexpr int kWide12Bits = 12;
+constexpr int kWide12Waves = 16;
+constexpr int kWide12ChunkBits = 19;
+constexpr uint64_t kW12Pairs0 = 0xA191817161514130ull;   // (0,3) (1,4) (1,5) (1,6) (1,7) (1,8) (1,9) (1,10)
+constexpr uint64_t kW12Pairs1 = 0xB3A39383736353B1ull;   // (1,11) (3,5) (3,6) (3,7) (3,8) (3,9) (3,10) (3,11)
 
 struct BlockGeometry {
     int pos[8];

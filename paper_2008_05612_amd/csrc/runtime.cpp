@@ -142,12 +142,14 @@ extern "C" {
 
 hp_status hp_blocked_select(int nw, int mode)
 {
-    if (nw != 2 && nw != 4 && nw != 8)
-        return fail(HP_EINVAL, "blocked form: waves per workgroup must be 2, 4 or 8");
+    if (nw != 2 && nw != 4 && nw != 8 && nw != 16)
+        return fail(HP_EINVAL, "blocked form: waves per workgroup must be 2, 4, 8 or 16");
     if (mode < -1 || mode > 3)
         return fail(HP_EINVAL, "blocked form: staging mode must be -1, 0, 1, 2 or 3");
-    if (mode == 3 && nw != 4)
-        return fail(HP_EINVAL, "blocked form: wide blocks (mode 3) run 4 waves per workgroup");
+    if (mode == 3 && nw != 4 && nw != 16)
+        return fail(HP_EINVAL, "blocked form: wide blocks (mode 3) run 4 or 16 waves per workgroup");
+    if (nw == 16 && mode != 3)
+        return fail(HP_EINVAL, "blocked form: 16 waves per workgroup only with wide blocks (mode 3)");
     g_blocked_nw.store(nw);
     g_blocked_mode.store(mode);
     return HP_OK;

@@ -677,33 +677,39 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
         }
     }
 
-    // Wide blocks (pure pair energies), two geometries: plain (the low 10
-    // monomers vary) and reversal-canonical (the 10 around the middle; see
-    // hp_internal.h).  Wave w of the workgroup holds the 256 sequences whose
-    // varying monomers 8 and 9 are the bits of w.  Same first-product matrix
-    // and key scale as above; the virtual rows are m = 0 the block term,
-    // 1 .. 10 the weight of varying monomer m - 1, 11 .. 26 the varying pairs
-    // (kLow10Pairs, or kMid10OddPairs for odd N canonical), 27 and 28 the
-    // index bytes.  Lane l of tile t of wave w holds block sequence
-    // x = 256 w + 32 t + (l & 31) and its byte q the indicator of row
-    // m = 8 (q / 4) + 4 (l / 32) + q % 4.
+    // Wide blocks (pure pair energies), three geometries: plain (the low 10
+    // monomers vary), reversal-canonical (the 10 around the middle) and
+    // plain 12 (monomers 0 .. 4 and 6, 8, .., 18; N >= 19), see
+    // hp_internal.h.  Wave w of the workgroup holds the 256 sequences whose
+    // varying monomers above the low 8 are the bits of w (4 waves, or 16 for
+    // plain 12).  Same first-product matrix and key scale as above; the
+    // virtual rows are m = 0 the block term, 1 .. nb the weight of varying
+    // monomer m - 1, then the 16 varying pairs (kLow10Pairs, kMid10OddPairs
+    // for odd N canonical, kW12Pairs), then the two index bytes.  Lane l of
+    // tile t of wave w holds block sequence x = 256 w + 32 t + (l & 31) and
+    // its byte q the indicator of row m = 8 (q / 4) + 4 (l / 32) + q % 4.
     s->wide_ok = false;
     s->wide_s2.clear();
     const int wodd = N & 1;
     const int whalf = N >= kWideBits ? (N - kWideBits - wodd) / 2 : 0;
-    auto wide_pos = [&](int g, int x) { return g == 0 ? x : whalf + x + (x >= 5 ? wodd : 0); };
+    const int n_geom = N >= kWide12ChunkBits ? 3 : 2;
+    auto wide_nb = [&](int g) { return g == 2 ? kWide12Bits : kWideBits; };
+    auto wide_pos = [&](int g, int x) {
+        return g == 0 ? x : g == 1 ? whalf + x + (x >= 5 ? wodd : 0) : (x < 5 ? x : 2 * x - 4);
+    };
     auto wide_pair = [&](int g, int p) {
-        const uint64_t w = (g == 1 && wodd) ? (p < 8 ? kMid10OddPairs0 : kMid10OddPairs1)
-                                            : (p < 8 ? kLow10Pairs0 : kLow10Pairs1);
+        const uint64_t w = g == 2 ? (p < 8 ? kW12Pairs0 : kW12Pairs1)
+                           : (g == 1 && wodd) ? (p < 8 ? kMid10OddPairs0 : kMid10OddPairs1)
+                                              : (p < 8 ? kLow10Pairs0 : kLow10Pairs1);
         return int((w >> (8 * (p & 7))) & 0xffu);
     };
     if (s->blk_ok && B == 0 && N >= kWideBits) {
         int maxw = 0;   // largest weight of a varying monomer (all outer monomers H)
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < n_geom; ++g) {
             bool vary[64] = {};
-            for (int x = 0; x < kWideBits; ++x)
+            for (int x = 0; x < wide_nb(g); ++x)
                 vary[wide_pos(g, x)] = true;
-            for (int x = 0; x < kWideBits; ++x) {
+            for (int x = 0; x < wide_nb(g); ++x) {
                 const int v = wide_pos(g, x);
                 for (uint32_t c = 0; c < n_conf; ++c) {
                     int with_outer = 0;
@@ -719,31 +725,35 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
         s->wide_ok = int64_t(s->blk_coef) * maxw <= 128;
     }
     if (s->wide_ok) {
-        s->wide_s2.assign(2 * 4 * 8 * 64 * 16, 0);
-        for (int g = 0; g < 2; ++g)
-            for (int w = 0; w < 4; ++w)
-                for (int t = 0; t < 8; ++t)
-                    for (int lane = 0; lane < 64; ++lane) {
-                        const int x = 256 * w + 32 * t + (lane & 31), half = lane >> 5;
-                        for (int q = 0; q < 16; ++q) {
-                            const int m = 8 * (q / 4) + 4 * half + q % 4;
-                            int v = 0;
-                            if (m == 0) {
-                                v = -128;
-                            } else if (m < 11) {
-                                v = ((x >> (m - 1)) & 1) ? -128 : 0;
-                            } else if (m < 27) {
-                                const int pr = wide_pair(g, m - 11);
-                                v = ((x >> (pr & 15)) & (x >> (pr >> 4)) & 1) ? -128 : 0;
-                            } else if (m == 27) {
-                                v = 1;
-                            } else if (m == 28) {
-                                v = -128;
-                            }
-                            s->wide_s2[(((size_t(g) * 4 + w) * 8 + t) * 64 + lane) * 16 + q] =
-                                static_cast<int8_t>(v);
+        const int n_waves = n_geom == 3 ? 4 + 4 + kWide12Waves : 4 + 4;
+        s->wide_s2.assign(size_t(n_waves) * 8 * 64 * 16, 0);
+        for (int slot = 0; slot < n_waves; ++slot) {
+            const int g = slot < 4 ? 0 : slot < 8 ? 1 : 2;
+            const int w = slot < 8 ? slot & 3 : slot - 8;
+            const int row_vv = 1 + wide_nb(g), row_idx = row_vv + 16;
+            for (int t = 0; t < 8; ++t)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int x = 256 * w + 32 * t + (lane & 31), half = lane >> 5;
+                    for (int q = 0; q < 16; ++q) {
+                        const int m = 8 * (q / 4) + 4 * half + q % 4;
+                        int v = 0;
+                        if (m == 0) {
+                            v = -128;
+                        } else if (m < row_vv) {
+                            v = ((x >> (m - 1)) & 1) ? -128 : 0;
+                        } else if (m < row_idx) {
+                            const int pr = wide_pair(g, m - row_vv);
+                            v = ((x >> (pr & 15)) & (x >> (pr >> 4)) & 1) ? -128 : 0;
+                        } else if (m == row_idx) {
+                            v = 1;
+                        } else if (m == row_idx + 1) {
+                            v = -128;
                         }
+                        s->wide_s2[((size_t(slot) * 8 + t) * 64 + lane) * 16 + q] =
+                            static_cast<int8_t>(v);
                     }
+                }
+        }
     }
 
     // pair table for the popcount form, 4 bytes per row (i, j, 0, 0)

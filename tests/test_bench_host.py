@@ -7,7 +7,7 @@ import bench
 
 
 def test_summary_file_per_kernel_family():
-    assert bench._summary_name("k_gemm_wide<5>", "hbm_traffic") == \
+    assert bench._summary_name("k_gemm_wide12<5>", "hbm_traffic") == \
         "k_gemm_wide_3x3x3_hbm_traffic.txt"
     assert bench._summary_name("k_gemm_blk<5,4,2>", "issue_counters") == \
         "k_gemm_blk_3x3x3_issue_counters.txt"
@@ -17,12 +17,13 @@ def test_recorded_figures_tied_to_kernel_and_sources():
     path = os.path.join(bench.ROOT, "profiles", "k_gemm_wide_3x3x3_hbm_traffic.txt")
     assert os.path.exists(path)
     f = bench._summary_fields("k_gemm_wide_3x3x3_hbm_traffic.txt")
-    assert f["kernel"] == "k_gemm_wide<5>"
+    kname = f["kernel"]
+    assert kname in ("k_gemm_wide<5>", "k_gemm_wide12<5>")
     sha = f["source_sha"]
-    assert bench.recorded_traffic("k_gemm_wide<5>", sha) == float(f["traffic_bytes_per_launch"])
+    assert bench.recorded_traffic(kname, sha) == float(f["traffic_bytes_per_launch"])
     # another kernel, or another build of the kernel sources: no figure
-    assert bench.recorded_traffic("k_gemm_wide<10>", sha) is None
-    assert bench.recorded_traffic("k_gemm_wide<5>", "0" * 16) is None
-    assert bench.recorded_issue("k_gemm_wide<5>", "0" * 16) == {"blocked_issue_counters": None}
-    got = bench.recorded_issue("k_gemm_wide<5>", sha)["blocked_issue_counters"]
+    assert bench.recorded_traffic(kname.replace("<5>", "<10>"), sha) is None
+    assert bench.recorded_traffic(kname, "0" * 16) is None
+    assert bench.recorded_issue(kname, "0" * 16) == {"blocked_issue_counters": None}
+    got = bench.recorded_issue(kname, sha)["blocked_issue_counters"]
     assert got is not None and got["mfma_per_wave_tile"] > 0

@@ -311,3 +311,69 @@ def test_wide_full_map_equals_popcount(wide, dims):
     o0, d0, n0 = _full_map_invariants(dims, hp.FORM_POPCOUNT)
     assert torch.equal(o0, o2)
     assert np.array_equal(d0, d2) and n0 == n2
+
+
+# ---------------------------------------------------------------------------
+# wide blocks of 4096 sequences (16 waves, selected with nw 16): plain ranges
+# whose ends are multiples of 2^19 on lattices with N >= 19
+# ---------------------------------------------------------------------------
+
+C19 = 1 << 19
+
+
+@pytest.fixture()
+def wide16():
+    keep = hp.hp_blocked_selected()
+    hp.hp_blocked_select(16, 3)
+    yield
+    hp.hp_blocked_select(*keep)
+
+
+@pytest.mark.parametrize("dims,lo,hi", [((5, 5, 1), C19, 2 * C19), ((2, 3, 4), 0, C19)])
+def test_wide12_chunk_matches_oracle(wide16, dims, lo, hi):
+    """One 2^19 chunk (128 blocks of 4096) against the oracle, every sequence."""
+    _assert_equal(run(dims, BLK, lo, hi), _oracle(dims, lo, hi))
+
+
+@pytest.mark.parametrize("dims,lo,hi", [((2, 3, 4), 3 * C19, 5 * C19),
+                                        ((3, 3, 3), 37 * C19, 39 * C19),
+                                        ((6, 6, 1), (1 << 35) - C19, (1 << 35) + C19)])
+def test_wide12_chunks_equal_popcount(wide16, dims, lo, hi):
+    """Several chunks (6x6: across the middle of the sequence space, K_pad 320)
+    equal the popcount form's map, energies and histogram bit for bit, and
+    the same range cut one sequence short (blocks of 1024) agrees too."""
+    a = run(dims, BLK, lo, hi)
+    b = run(dims, hp.FORM_POPCOUNT, lo, hi)
+    for k in ("out", "emin", "desig"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["nondesign"] == b["nondesign"]
+    c = run(dims, BLK, lo + 1, hi)
+    assert np.array_equal(c["out"], a["out"][1:]) and np.array_equal(c["emin"], a["emin"][1:])
+
+
+def test_wide12_gap_threshold(wide16):
+    import torch
+    dims, lo, hi = (5, 5, 1), 2 * C19, 3 * C19
+    s = hp.Structures(*dims)
+    ws = s.workspace()
+    st = oracle.structures(*dims)
+    for th in (2, 3):
+        o = torch.full((hi - lo,), -7, dtype=torch.int16, device="cuda")
+        g = torch.zeros(hi - lo, dtype=torch.uint8, device="cuda")
+        print("gap", dims, lo, hi, th, flush=True)
+        hp.hp_enumerate_gap(s, ws, BLK, lo, hi, th, o, None, g)
+        torch.cuda.synchronize()
+        gs = oracle.ground_states_gap(st, np.arange(lo, hi, dtype=np.uint64), threshold=th)
+        assert np.array_equal(o.cpu().numpy().view(np.uint16), gs.out), th
+        assert np.array_equal(g.cpu().numpy(), gs.gap), th
+
+
+def test_wide12_full_3x3x3_map_equals_default(wide16):
+    """The full 3x3x3 map with 16-wave blocks of 4096 equals the default
+    shape's map and histogram bit for bit."""
+    import torch
+    o16, d16, n16 = _full_map_invariants((3, 3, 3), BLK)
+    hp.hp_blocked_select(4, -1)
+    o4, d4, n4 = _full_map_invariants((3, 3, 3), BLK)
+    assert torch.equal(o16, o4)
+    assert np.array_equal(d16, d4) and n16 == n4
