@@ -68,10 +68,12 @@ def parse():
                     help="time every launch shape of the blocked form and every tile shape of "
                          "the dense form first, and use the fastest")
     ap.add_argument("--nw", type=int, default=4,
-                    help="waves per workgroup of the blocked form (2, 4 or 8)")
+                    help="waves per workgroup of the blocked form (2, 4 or 8; 16 with "
+                         "--blk-mode 3)")
     ap.add_argument("--blk-mode", type=int, default=-1,
                     help="staging mode of the blocked form (0 double-buffered, 1 pipelined, "
-                         "2 second operand in LDS, -1 by product depth)")
+                         "2 second operand in LDS, 3 wide blocks, -1 wide blocks where they "
+                         "apply, else by product depth)")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: no extras, no CPU baseline, plus one dense-form "
                          "full map and a 256 MiB device copy used to calibrate the HBM byte "
@@ -125,8 +127,8 @@ def main():
     hp.hp_blocked_select(args.nw, args.blk_mode)
     nw = args.nw
     # the staging the library takes for mode -1: wide blocks where they apply
-    # (pure pair energies, N >= 10, 4 waves), else by product depth
-    wide = s.unary_rows == 0 and s.N >= 10 and nw == 4
+    # (pure pair energies, N >= 10, 4 or 16 waves), else by product depth
+    wide = s.unary_rows == 0 and s.N >= 10 and nw in (4, 16)
     blk_mode = (args.blk_mode if args.blk_mode >= 0 and (args.blk_mode != 3 or wide)
                 else (3 if wide else (2 if s.K_pad <= 192 else 0)))
     if args.autotune:
