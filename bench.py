@@ -103,7 +103,7 @@ class Timer:
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sequence range would shard across GPUs; see the design notes).",
               file=sys.stderr)
         sys.exit(2)

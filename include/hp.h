@@ -53,7 +53,7 @@ typedef enum {
     HP_ENOMEM = -2,       /* host allocation failed */
     HP_EDEVICE = -3,      /* a HIP call failed */
     HP_ERANGE = -4,       /* problem too large for the id or index types */
-    HP_EUNSUPPORTED = -5  /* valid request this build does not handle */
+    HP_EUNSUPPORTED = -5  /* valid request the library does not handle */
 } hp_status;
 
 #define HP_NONE 0xFFFFu

@@ -58,7 +58,7 @@ def designability_sha(d: np.ndarray) -> str:
 def compare(out, canon=None):
     """Compare the device map `out` (int16/uint16 view, 2^27 entries) with
     every chunk of the fixture.  Returns (chunks checked, mismatching chunk
-    indices, full-map hash verdict or None when the fixture is partial)."""
+    indices, full-map hash result or None when the fixture is partial)."""
     chunks, whole = load()
     if canon is None:
         canon = canonical_sequences(out.device)
