@@ -485,8 +485,9 @@ hp_status hp_phi_sparse(const hp_structs *s, const uint64_t *d_counts, uint64_t 
 /*
  * hp_components -- neutral networks: connected components of the subgraph
  * of the N-cube of sequences (edges = single point mutations) induced on
- * genotypes of equal designing phenotype (Introduction, "spaghetti vs plum
- * pudding"; the text on neutral networks in the results).
+ * genotypes of equal designing phenotype (the Introduction's two pictures
+ * of how phenotypes lie in genotype space, and neutral networks in the
+ * Results).
  *   d_labels[g]   smallest genotype of g's component, 0xFFFFFFFF if g is
  *                 deleterious (2^N entries, overwritten);
  *   d_compsize[g] size of the component whose smallest genotype is g, 0 for
