@@ -116,7 +116,7 @@ def test_blocked_pair_table_weight_three(dims, lo, hi):
 
 
 @pytest.mark.parametrize("nw,mode", [(2, 0), (4, 0), (8, 0), (2, 1), (4, 1), (8, 1), (2, 2), (4, 2),
-                                     (8, 2), (4, 3)])
+                                     (8, 2), (4, 3), (16, 3)])
 def test_blocked_every_launch_shape(nw, mode):
     keep = hp.hp_blocked_selected()
     try:
@@ -377,3 +377,15 @@ def test_wide12_full_3x3x3_map_equals_default(wide16):
     o4, d4, n4 = _full_map_invariants((3, 3, 3), BLK)
     assert torch.equal(o16, o4)
     assert np.array_equal(d16, d4) and n16 == n4
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 1), (4, 4, 1), (2, 3, 3)])
+def test_wide16_selection_on_canonical_blocks(wide16, dims):
+    """With 16 waves selected, reversal-canonical blocks keep their own
+    geometry: the symmetric map still equals the oracle's."""
+    s = hp.Structures(*dims)
+    nb = hp.hp_canonical_block_count(s)
+    s, out, emin, d, nd = _sym_run(dims, 0, nb)
+    _assert_equal({"out": out.cpu().numpy().view(np.uint16), "emin": emin.cpu().numpy(),
+                   "desig": d.cpu().numpy().view(np.uint64), "nondesign": int(nd.item())},
+                  _oracle(dims, 0, 1 << s.N))
