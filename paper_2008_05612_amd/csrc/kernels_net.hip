@@ -538,6 +538,38 @@ __global__ __launch_bounds__(256) void k_uf_count(const uint16_t *__restrict__ m
     }
 }
 
+// Eight genotypes per lane (map and labels read as vectors).
+__global__ __launch_bounds__(256) void k_uf_count8(const uint4 *__restrict__ m4,
+                                                   const uint4 *__restrict__ labels4,
+                                                   const uint32_t *__restrict__ compsize,
+                                                   uint32_t *ncomp, uint32_t *largest,
+                                                   int n_class, uint64_t n8)
+{
+    for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n8;
+         k += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t q[8];
+        unpack8(m4[k], q);
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            any |= int(q[r]) < n_class;
+        if (!any)
+            continue;
+        const uint4 la = labels4[2 * k], lb = labels4[2 * k + 1];
+        const uint32_t lab[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
+        const uint32_t g0 = uint32_t(8 * k);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (int(q[r]) >= n_class || lab[r] != g0 + uint32_t(r))
+                continue;
+            if (ncomp)
+                atomicAdd(&ncomp[q[r]], 1u);
+            if (largest)
+                atomicMax(&largest[q[r]], compsize[g0 + r]);
+        }
+    }
+}
+
 hipError_t launch_components(const uint16_t *map, int N, uint32_t *labels, uint32_t *compsize,
                              uint32_t *ncomp, uint32_t *largest, int n_class, hipStream_t st)
 {
@@ -548,15 +580,27 @@ hipError_t launch_components(const uint16_t *map, int N, uint32_t *labels, uint3
         return e;
     if (largest && (e = launch_fill_u32(largest, 0u, uint64_t(n_class), st)) != hipSuccess)
         return e;
+    // eight genotypes per lane where the map (and, for the count, the labels)
+    // are 16-byte vectors; one genotype per lane otherwise.  The init pass
+    // stays one genotype per lane: its 4-byte stores are contiguous per wave
+    // (measured 0.30 ms against 0.36 ms for 8 per lane on the 3x3x3 map).
+    const bool v8 = use_geno8(map, N) && (reinterpret_cast<uintptr_t>(labels) & 15u) == 0;
+    const uint64_t n8 = total / 8;
+    const dim3 grid8(grid_for(n8, 256));
+    const uint4 *m4 = reinterpret_cast<const uint4 *>(map);
     hipLaunchKernelGGL(k_uf_init, grid, block, 0, st, map, labels, compsize, total);
     if (use_geno8(map, N))
-        hipLaunchKernelGGL(k_uf_hook8, dim3(grid_for(total / 8, 256)), block, 0, st,
-                           reinterpret_cast<const uint4 *>(map), N, labels, total / 8);
+        hipLaunchKernelGGL(k_uf_hook8, grid8, block, 0, st, m4, N, labels, n8);
     else
         hipLaunchKernelGGL(k_uf_hook, grid, block, 0, st, map, N, labels, total);
     hipLaunchKernelGGL(k_uf_compress, grid, block, 0, st, map, labels, compsize, total);
-    hipLaunchKernelGGL(k_uf_count, grid, block, 0, st, map, labels, compsize, ncomp, largest,
-                       n_class, total);
+    if (v8)
+        hipLaunchKernelGGL(k_uf_count8, grid8, block, 0, st, m4,
+                           reinterpret_cast<const uint4 *>(labels), compsize, ncomp, largest,
+                           n_class, n8);
+    else
+        hipLaunchKernelGGL(k_uf_count, grid, block, 0, st, map, labels, compsize, ncomp, largest,
+                           n_class, total);
     return hipGetLastError();
 }
 
