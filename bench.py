@@ -68,8 +68,7 @@ def parse():
                     help="time every launch shape of the blocked form and every tile shape of "
                          "the dense form first, and use the fastest")
     ap.add_argument("--nw", type=int, default=4,
-                    help="waves per workgroup of the blocked form (2, 4 or 8; 16 with "
-                         "--blk-mode 3)")
+                    help="waves per workgroup of the blocked form (2, 4 or 8)")
     ap.add_argument("--blk-mode", type=int, default=-1,
                     help="staging mode of the blocked form (0 double-buffered, 1 pipelined, "
                          "2 second operand in LDS, 3 wide blocks, -1 wide blocks where they "
@@ -127,18 +126,19 @@ def main():
     hp.hp_blocked_select(args.nw, args.blk_mode)
     nw = args.nw
     # the staging the library takes for mode -1: wide blocks where they apply
-    # (pure pair energies, N >= 10, 4 or 16 waves), else by product depth
-    wide = s.unary_rows == 0 and s.N >= 10 and nw in (4, 16)
+    # (pure pair energies, N >= 10, 4 or 8 waves), else by product depth
+    wide = s.unary_rows == 0 and s.N >= 10 and nw in (4, 8)
     blk_mode = (args.blk_mode if args.blk_mode >= 0 and (args.blk_mode != 3 or wide)
                 else (3 if wide else (2 if s.K_pad <= 192 else 0)))
     if args.autotune:
         _, tune_ms = hp.hp_autotune(s, ws, 0, 1 << 20, repeats=2)
         (nw, blk_mode), blk_ms = hp.hp_autotune_blocked(s, ws, 0, 1 << 22, repeats=2)
         tune_ms = {"dense": tune_ms, "blocked": blk_ms}
-    # with 16 waves selected, the whole map (one range cut at a multiple of
-    # 2^19) takes wide blocks of 4096 sequences where N >= 19
-    wide12 = blk_mode == 3 and nw == 16 and s.N >= 19
-    kname = ("k_gemm_wide12<%d>" % (s.K_pad // 32) if wide12
+    # wide blocks with 8 waves (the default, or --nw 8): the whole map, one
+    # range cut at a multiple of 2^17, takes blocks of 2048 sequences where
+    # N >= 17; --nw 4 --blk-mode 3 keeps blocks of 1024 on 4 waves
+    wide8 = blk_mode == 3 and (args.blk_mode < 0 or nw == 8) and s.N >= 17
+    kname = ("k_gemm_wide_w8<%d>" % (s.K_pad // 32) if wide8
              else "k_gemm_wide<%d>" % (s.K_pad // 32) if blk_mode == 3
              else "k_gemm_blk<%d,%d,%d>" % (s.K_pad // 32, nw, blk_mode))
     pairs = total * n_conf
@@ -195,10 +195,10 @@ def main():
     achieved_tops = method_ops / (enum_ms * 1e-3) / 1e12
     # MFMA work the blocked form issues: one depth-32 product per pair, plus
     # the per-block first product (K_pad deep, 32 virtual rows) per
-    # conformation tile, once per block of 256 sequences, or of 1024 or 4096
+    # conformation tile, once per block of 256 sequences, or of 1024 or 2048
     # for wide blocks
     n_tiles = (n_conf + 31) // 32
-    block_seqs = 4096 if wide12 else 1024 if blk_mode == 3 else 256
+    block_seqs = 2048 if wide8 else 1024 if blk_mode == 3 else 256
     blk_mfma_ops = (2.0 * 32 * pairs +
                     2.0 * s.K_pad * 32 * 32 * n_tiles * (total // block_seqs))
     evals_per_s = pairs / (ms_step * 1e-3)
@@ -294,7 +294,7 @@ def _summary_fields(name):
 
 def _summary_name(kname, what):
     """profiles/ file of the counter summary `what` for kernel `kname`
-    (k_gemm_wide<KB>, k_gemm_wide12<KB> or k_gemm_blk<KB,NW,MODE>) on the
+    (k_gemm_wide<KB>, k_gemm_wide_w8<KB> or k_gemm_blk<KB,NW,MODE>) on the
     3x3x3 map."""
     family = "k_gemm_wide" if kname.startswith("k_gemm_wide") else "k_gemm_blk"
     return "%s_3x3x3_%s.txt" % (family, what)

@@ -362,30 +362,29 @@ hp_status hp_enumerate_batch_static(const hp_job *jobs, int njobs, int form, voi
 /*
  * Launch shape of HP_FORM_BLOCKED_I8: every wave scores one block of 256
  * sequences.  hp_blocked_select sets, process-wide, the waves per workgroup
- * nw (2, 4 or 8, or 16 with mode 3; default 4; the waves of a workgroup share each staged
+ * nw (2, 4 or 8; default 4; the waves of a workgroup share each staged
  * contact tile) and the staging mode (0: double-buffered LDS; 1:
  * triple-buffered LDS with the block-level product of the next tile issued
  * while the current tile's keys are updated; 2: as 0, with the per-sequence
  * operand of the second product read from LDS instead of held in registers;
- * 3: wide blocks, 1024 sequences sharing every monomer above the low 10 per
- * workgroup of 4 waves, one first product per conformation tile shared by
- * the waves; with nw = 16, where both ends of the range are multiples of
- * 2^19 and N >= 19, 4096 sequences (monomers 0 .. 4 and 6, 8, .., 18) per
- * workgroup of 16 waves (a quarter of the contact-matrix reads, slower on
- * the full 3x3x3 map) -- pure pair energies over plain ranges only,
- * elsewhere mode 3 acts as -1; -1, default: 3 where wide blocks apply, else
- * 2 for K_pad <= 192, else 0).  hp_blocked_selected
+ * 3: wide blocks, one first product per conformation tile shared by the
+ * waves of a workgroup: with nw = 8, where both ends of the range are
+ * multiples of 2^17 and N >= 17, 2048 sequences (monomers 0 .. 4 and 6, 8,
+ * .., 16 vary) per workgroup of 8 waves, otherwise 1024 sequences sharing
+ * every monomer above the low 10 per workgroup of 4 waves; with nw = 4
+ * always the latter -- pure pair energies over plain ranges only, elsewhere
+ * mode 3 acts as -1; -1, default: 3 with 8 waves where wide blocks apply,
+ * else 2 for K_pad <= 192, else 0).  hp_blocked_selected
  * reports them (either pointer may be NULL).  Results never depend on the
  * shape.
- * Errors: HP_EINVAL for another value, mode 3 with nw other than 4 or 16, or
- * nw = 16 with another mode.
+ * Errors: HP_EINVAL for another value, or mode 3 with nw = 2.
  */
 hp_status hp_blocked_select(int nw, int mode);
 void hp_blocked_selected(int *nw, int *mode);
 /*
  * hp_autotune_blocked -- time the launch shapes of HP_FORM_BLOCKED_I8
  * (entries 0 .. 8: nw = 2, 4, 8 x mode = 0, 1, 2, entry i is nw =
- * {2,4,8}[i / 3], mode = i % 3; entry 9: wide blocks, nw 4, mode 3, where
+ * {2,4,8}[i / 3], mode = i % 3; entry 9: wide blocks, nw 8, mode 3, where
  * they apply, else ms[9] = -1) on sequences [seq_lo, seq_lo + n_seq) (no
  * outputs written, `repeats` launches each after one warm-up), select the
  * fastest process-wide, and report per-shape milliseconds in ms[10] and the

@@ -509,19 +509,19 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_blk_batch(BatchHeader *hdr, in
 //   0  plain ranges, 1024 sequences (the low 10 monomers), 4 waves;
 //   1  reversal-canonical blocks, 1024 sequences (the 10 around the middle),
 //      4 waves;
-//   2  plain ranges cut at multiples of 2^19 when 16 waves are selected,
-//      4096 sequences (monomers 0 .. 4 and the even ones 6 .. 18: equal
-//      parity never touches, so 12 varying monomers still have only 16
-//      pairs), 16 waves, so a first product serves 4096 sequences.
+//   2  plain ranges cut at multiples of 2^17, 2048 sequences (monomers 0 .. 4
+//      and the even ones 6 .. 16: equal parity never touches, so 11 varying
+//      monomers have only 14 pairs), 8 waves, so a first product serves 2048
+//      sequences; the default where it applies.
 // Per 32 x 32 tile the matrix pipe runs one depth-32 product plus 1/NW of the
 // first product's K_pad/32, and the first product is packed once per
 // workgroup.
 // ---------------------------------------------------------------------------
 
 template <int G>
-constexpr int wide_bits() { return G == 2 ? kWide12Bits : kWideBits; }
+constexpr int wide_bits() { return G == 2 ? kWide11Bits : kWideBits; }
 template <int G>
-constexpr int wide_waves() { return G == 2 ? kWide12Waves : 4; }
+constexpr int wide_waves() { return G == 2 ? kWide11Waves : 4; }
 // virtual rows: 0 block term, 1 .. nb weights, then 16 pairs, then 2 index rows
 template <int G>
 constexpr int wide_row_vv() { return 1 + wide_bits<G>(); }
@@ -530,7 +530,7 @@ constexpr int wide_row_idx() { return wide_row_vv<G>() + 16; }
 
 // Varying monomer x of a wide block: G 0 the low 10; G 1 the 10 around the
 // middle, h = j.half_bits outer monomers on each side (and, for odd N, the
-// middle monomer h + 5 outer as well); G 2 monomers 0 .. 4, 6, 8, .., 18.
+// middle monomer h + 5 outer as well); G 2 monomers 0 .. 4, 6, 8, .., 16.
 template <int G>
 __device__ __forceinline__ int wide_pos(const EnumJob &j, int x)
 {
@@ -548,7 +548,7 @@ __device__ __forceinline__ bool wide_varies(const EnumJob &j, int i)
     if constexpr (G == 0) {
         return i < kWideBits;
     } else if constexpr (G == 2) {
-        return i < 5 || (i >= 6 && i <= 18 && !(i & 1));
+        return i < 5 || (i >= 6 && i <= 16 && !(i & 1));
     } else {
         const int h = j.half_bits, odd = j.N & 1;
         return i >= h && i < h + kWideBits + odd && !(odd && i == h + 5);
@@ -559,7 +559,7 @@ __device__ __forceinline__ bool wide_varies(const EnumJob &j, int i)
 template <int G>
 __device__ __forceinline__ int wide_pair(const EnumJob &j, int p)
 {
-    const uint64_t w = G == 2                     ? (p < 8 ? kW12Pairs0 : kW12Pairs1)
+    const uint64_t w = G == 2                     ? (p < 8 ? kW11Pairs0 : kW11Pairs1)
                        : (G == 1 && (j.N & 1)) ? (p < 8 ? kMid10OddPairs0 : kMid10OddPairs1)
                                                  : (p < 8 ? kLow10Pairs0 : kLow10Pairs1);
     return int((w >> (8 * (p & 7))) & 0xffu);
@@ -651,20 +651,20 @@ __device__ __forceinline__ uint64_t wide_canonical_outer(const EnumJob &j, uint6
     return (uint64_t(a) << (h + kWideBits + odd)) | (uint64_t(m) << (h + 5)) | b;
 }
 
-// Plain-12 block index t -> outer bits: chunk t >> 7 of 2^19 sequences, and
-// within it bits 0 .. 6 of t on the outer monomers 5, 7, .., 17.
-__device__ __forceinline__ uint64_t wide12_outer(uint64_t t)
+// Plain-11 block index t -> outer bits: chunk t >> 6 of 2^17 sequences, and
+// within it bits 0 .. 5 of t on the outer monomers 5, 7, .., 15.
+__device__ __forceinline__ uint64_t wide11_outer(uint64_t t)
 {
-    uint64_t o = (t >> 7) << kWide12ChunkBits;
+    uint64_t o = (t >> 6) << kWide11ChunkBits;
 #pragma unroll
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < 6; ++k)
         o |= ((t >> k) & 1u) << (5 + 2 * k);
     return o;
 }
 
 // The work of one workgroup: wave w of NW = wide_waves<G>() scores the 256
 // sequences x = 256 w + 32 t + col (t = 0 .. 7) of block `blk` (plain 10:
-// sequence >> 10; canonical: canonical block index; plain 12: chunk << 7 |
+// sequence >> 10; canonical: canonical block index; plain 11: chunk << 6 |
 // the outer bits of the chunk).  vlds holds the block's first-product
 // fragments, a2s the packed first products of two groups of NW tiles
 // ([2][NW][64]), gbs every lane's running top-2 keys ([NW][8][64]).
@@ -675,11 +675,11 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
     constexpr int NW = wide_waves<G>();
     bool diag = false;
     const uint64_t outer = G == 1   ? wide_canonical_outer(j, blk, &diag)
-                           : G == 2 ? wide12_outer(blk)
+                           : G == 2 ? wide11_outer(blk)
                                     : blk << kWideBits;
     // Contact tiles of the first product are loaded one group ahead into
     // registers for shallow products; deep ones (K_pad > 192, or > 160 with
-    // 16 waves) load right before use, which keeps four waves per SIMD.
+    // 8 waves) load right before use, which keeps four waves per SIMD.
     constexpr bool kPrefetch = KB <= (NW == 4 ? 6 : 5);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -798,7 +798,7 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
         } else if constexpr (G == 2) {
             uint64_t sq = outer | uint64_t(x & 31);
 #pragma unroll
-            for (int b = 5; b < kWide12Bits; ++b)
+            for (int b = 5; b < kWide11Bits; ++b)
                 sq |= uint64_t((x >> b) & 1) << wide_pos<2>(j, b);
             finish_sequence(j, sq, sq, sq, half == 0 && sq >= j.lo && sq < j.hi, gb[t], gs[t],
                             lane == 0, 1);
@@ -823,15 +823,15 @@ __global__ __launch_bounds__(256) void k_gemm_wide(EnumJob j)
                                  gbs);
 }
 
-// Plain ranges cut at multiples of 2^19: blocks of 4096 sequences, 16 waves
-// (one workgroup per CU: 101 KB of LDS at K_pad 160).
+// Plain ranges cut at multiples of 2^17: blocks of 2048 sequences, 8 waves
+// (two workgroups per CU: 53 KB of LDS each at K_pad 160).
 template <int KB>
-__global__ __launch_bounds__(1024) void k_gemm_wide12(EnumJob j)
+__global__ __launch_bounds__(512) void k_gemm_wide_w8(EnumJob j)
 {
     __shared__ v4i vlds[KB * 64];
-    __shared__ v4i a2s[2 * kWide12Waves * 64];
-    __shared__ int2 gbs[kWide12Waves * kBlkTiles * 64];
-    wide_body<KB, 2>(j, ((j.lo >> kWide12ChunkBits) << 7) + blockIdx.x, vlds, a2s, gbs);
+    __shared__ v4i a2s[2 * kWide11Waves * 64];
+    __shared__ int2 gbs[kWide11Waves * kBlkTiles * 64];
+    wide_body<KB, 2>(j, ((j.lo >> kWide11ChunkBits) << 6) + blockIdx.x, vlds, a2s, gbs);
 }
 
 // Batched wide blocks for jobs of one product depth: workgroup b scores the
@@ -866,27 +866,27 @@ hipError_t launch_wide_batch(BatchHeader *hdr, int item_lo, unsigned grid, hipSt
     return hipGetLastError();
 }
 
-// With 16 waves selected, plain ranges take blocks of 4096 when both ends
-// are multiples of 2^19 and monomer 18 exists; otherwise blocks of 1024
-// (4 waves), the default.  The 4096 geometry re-reads the contact matrix a
-// quarter as often and issues a quarter of the first products, but its one
-// workgroup per CU leaves nothing to run while the 16 waves meet at each
-// group's barrier: measured slower on the full 3x3x3 map.
-inline bool wide12_applies(const EnumJob &j)
+// With 8 waves allowed, plain ranges take blocks of 2048 when both ends are
+// multiples of 2^17 and monomer 16 exists; otherwise blocks of 1024 (4
+// waves).  The 2048 geometry issues half the first products and re-reads the
+// contact matrix half as often, and two workgroups per CU keep the SIMDs
+// busy while one meets at its group barrier (16 waves in one workgroup per
+// CU, tried, left them idle there).
+inline bool wide11_applies(const EnumJob &j)
 {
-    const uint64_t m = (uint64_t(1) << kWide12ChunkBits) - 1;
-    return j.N >= kWide12ChunkBits && j.hi > j.lo && (j.lo & m) == 0 && (j.hi & m) == 0;
+    const uint64_t m = (uint64_t(1) << kWide11ChunkBits) - 1;
+    return j.N >= kWide11ChunkBits && j.hi > j.lo && (j.lo & m) == 0 && (j.hi & m) == 0;
 }
 
 template <int KB>
-hipError_t launch_wide(const EnumJob &j, bool waves16, hipStream_t st)
+hipError_t launch_wide(const EnumJob &j, bool waves8, hipStream_t st)
 {
     if (j.mode == kSeqCanonical) {
         hipLaunchKernelGGL((k_gemm_wide<KB, true>), dim3(unsigned(j.hi - j.lo)), dim3(256), 0, st,
                            j);
-    } else if (waves16 && wide12_applies(j)) {
-        const uint64_t n = ((j.hi - j.lo) >> kWide12ChunkBits) << 7;
-        hipLaunchKernelGGL((k_gemm_wide12<KB>), dim3(unsigned(n)), dim3(1024), 0, st, j);
+    } else if (waves8 && wide11_applies(j)) {
+        const uint64_t n = ((j.hi - j.lo) >> kWide11ChunkBits) << 6;
+        hipLaunchKernelGGL((k_gemm_wide_w8<KB>), dim3(unsigned(n)), dim3(512), 0, st, j);
     } else {
         const uint64_t n = ((j.hi - 1) >> kWideBits) - (j.lo >> kWideBits) + 1;
         hipLaunchKernelGGL((k_gemm_wide<KB, false>), dim3(unsigned(n)), dim3(256), 0, st, j);
@@ -955,7 +955,7 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
     if (j.blk_ngroups > 0 || j.blk_coefB != 0)
         return launch_blk_unary<KB>(j, st);
     if (mode == kBlkStageWide)
-        return launch_wide<KB>(j, nw == 16, st);
+        return launch_wide<KB>(j, nw == 8, st);
     if (mode == kBlkLdsS2) {
         switch (nw) {
         case 2: return launch_blk_shape<KB, 2, kBlkLdsS2>(j, st);

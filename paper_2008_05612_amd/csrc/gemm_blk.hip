@@ -82,13 +82,16 @@ hipError_t launch_gemm_blocked(const EnumJob &j, int nw, int mode, hipStream_t s
     // where they apply (measured faster at every depth) and otherwise keeps
     // the second operand in LDS for shallow products
     const bool wide_ok = j.wide_s2 && j.mode == kSeqPlain && j.blk_ngroups == 0 &&
-                         j.blk_coefB == 0 && (nw == 4 || nw == 16);
+                         j.blk_coefB == 0;
+    // wide blocks: 8 waves (blocks of 2048 where the range allows) by default
+    // or when 8 waves are selected; 4 waves (blocks of 1024) when 4 are
+    const bool wide8 = mode < 0 || nw == 8;
     if (mode == kBlkStageWide && !wide_ok)
         mode = -1;
-    if (nw == 16 && mode != kBlkStageWide)
-        nw = 4;   // 16 waves exist only as wide blocks
     if (mode < 0)
         mode = wide_ok ? kBlkStageWide : (j.blk_KB <= 6 ? kBlkStageS2Lds : kBlkStageLds);
+    if (mode == kBlkStageWide)
+        nw = wide8 ? 8 : 4;
     if (j.blk_KB < 1 || j.blk_KB > kDepths)
         return hipErrorInvalidValue;
     return kBlocked[j.blk_KB](j, nw, mode, st);

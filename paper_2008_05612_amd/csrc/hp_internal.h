@@ -35,8 +35,8 @@ struct WsLayout {
     size_t gemm_a = 0;   // int8_t[n_tiles][K_pad/32][64 lanes][16]
     size_t gemm_b = 0;   // blocked form: int8_t[n_tiles][K_pad/32][64 lanes][16], or none
     size_t blk_s2 = 0;   // blocked form: int8_t[2 geometries][8 tiles][64 lanes][16], or none
-    size_t wide_s2 = 0;  // wide blocks: int8_t[4 + 4 + 16 waves][8 tiles][64 lanes][16] (geometries:
-                         // plain 10, canonical 10, plain 12), or none
+    size_t wide_s2 = 0;  // wide blocks: int8_t[4 + 4 + 8 waves][8 tiles][64 lanes][16] (geometries:
+                         // plain 10, canonical 10, plain 11), or none
     size_t total = 0;
 };
 
@@ -107,19 +107,20 @@ constexpr int kLow10NumPairs = 16;
 // with odd N (x-indices, same byte layout):
 constexpr uint64_t kMid10OddPairs0 = 0x7151806096854130ull;  // (0,3) (1,4) (5,8) (6,9) (0,6) (0,8) (1,5) (1,7)
 constexpr uint64_t kMid10OddPairs1 = 0x8464937353826291ull;  // (1,9) (2,6) (2,8) (3,5) (3,7) (3,9) (4,6) (4,8)
-// Wide blocks of 4096 sequences for plain ranges, scored by the 16 waves of
-// one workgroup: the 12 varying monomers are 0 .. 4 and the even monomers
-// 6, 8, .., 18 (pos(x) = x for x < 5, 2 x - 4 after).  Monomers of equal
+// Wide blocks of 2048 sequences for plain ranges, scored by the 8 waves of
+// one workgroup: the 11 varying monomers are 0 .. 4 and the even monomers
+// 6, 8, .., 16 (pos(x) = x for x < 5, 2 x - 4 after).  Monomers of equal
 // parity are never in contact (odd separation), so the only varying pairs
-// are (0,3), (1,4) and those of monomers 1 and 3 with the seven even ones:
-// 16 pairs, and base, 12 weights, 16 pairs and 2 index rows fill 31 of the
-// 32 virtual rows.  The outer monomers 5, 7, .., 17 of a 2^19-sequence
-// chunk index its 128 blocks.  Pairs as x-indices a | b << 4:
-constexpr int kWide12Bits = 12;
-constexpr int kWide12Waves = 16;
-constexpr int kWide12ChunkBits = 19;
-constexpr uint64_t kW12Pairs0 = 0xA191817161514130ull;   // (0,3) (1,4) (1,5) (1,6) (1,7) (1,8) (1,9) (1,10)
-constexpr uint64_t kW12Pairs1 = 0xB3A39383736353B1ull;   // (1,11) (3,5) (3,6) (3,7) (3,8) (3,9) (3,10) (3,11)
+// are (0,3), (1,4) and those of monomers 1 and 3 with the six even ones: 14
+// pairs, padded to 16 with two pairs of equal parity whose rows stay zero;
+// base, 11 weights, 16 pair rows and 2 index rows fill 30 of the 32 virtual
+// rows.  The outer monomers 5, 7, .., 15 of a 2^17-sequence chunk index its
+// 64 blocks.  Pairs as x-indices a | b << 4:
+constexpr int kWide11Bits = 11;
+constexpr int kWide11Waves = 8;
+constexpr int kWide11ChunkBits = 17;
+constexpr uint64_t kW11Pairs0 = 0xA191817161514130ull;   // (0,3) (1,4) (1,5) (1,6) (1,7) (1,8) (1,9) (1,10)
+constexpr uint64_t kW11Pairs1 = 0x4220A39383736353ull;   // (3,5) (3,6) (3,7) (3,8) (3,9) (3,10) (0,2) (2,4)
 
 struct BlockGeometry {
     int pos[8];

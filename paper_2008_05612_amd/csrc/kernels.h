@@ -43,8 +43,8 @@ struct EnumJob {
     int32_t blk_KB, blk_coefB, blk_ngroups;   // first-product depth / 32, m2 B, unary rows
     uint64_t blk_grp[3];                      // unary group of each outer monomer (4 bits)
     const int8_t *blk_s2;           // second-product operand of this geometry (8 x 64 x 16 B)
-    const int8_t *wide_s2;          // wide blocks: second-product operand ((4 + 4 + 16) waves
-                                    // x 8 x 64 x 16 B: plain 10, canonical 10 and plain 12
+    const int8_t *wide_s2;          // wide blocks: second-product operand ((4 + 4 + 8) waves
+                                    // x 8 x 64 x 16 B: plain 10, canonical 10 and plain 11
                                     // geometries), or null where wide blocks do not apply
 };
 

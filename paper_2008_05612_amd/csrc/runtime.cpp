@@ -142,14 +142,12 @@ extern "C" {
 
 hp_status hp_blocked_select(int nw, int mode)
 {
-    if (nw != 2 && nw != 4 && nw != 8 && nw != 16)
-        return fail(HP_EINVAL, "blocked form: waves per workgroup must be 2, 4, 8 or 16");
+    if (nw != 2 && nw != 4 && nw != 8)
+        return fail(HP_EINVAL, "blocked form: waves per workgroup must be 2, 4 or 8");
     if (mode < -1 || mode > 3)
         return fail(HP_EINVAL, "blocked form: staging mode must be -1, 0, 1, 2 or 3");
-    if (mode == 3 && nw != 4 && nw != 16)
-        return fail(HP_EINVAL, "blocked form: wide blocks (mode 3) run 4 or 16 waves per workgroup");
-    if (nw == 16 && mode != 3)
-        return fail(HP_EINVAL, "blocked form: 16 waves per workgroup only with wide blocks (mode 3)");
+    if (mode == 3 && nw != 4 && nw != 8)
+        return fail(HP_EINVAL, "blocked form: wide blocks (mode 3) run 4 or 8 waves per workgroup");
     g_blocked_nw.store(nw);
     g_blocked_mode.store(mode);
     return HP_OK;
@@ -286,8 +284,9 @@ hp_status hp_autotune_blocked(const hp_structs *s, const void *d_ws, uint64_t se
     float best_t = 0.f;
     EnumJob j = make_enum_job(s, d_ws, seq_lo, seq_lo + n_seq, nullptr, nullptr, nullptr, nullptr);
     for (int i = 0; i < 10 && err == hipSuccess; ++i) {
-        // shapes 0 .. 8: nw x staging mode; shape 9: wide blocks, where they apply
-        const int nw = i < 9 ? kNW[i / 3] : 4, mode = i < 9 ? i % 3 : 3;
+        // shapes 0 .. 8: nw x staging mode; shape 9: wide blocks, where they
+        // apply (8 waves: blocks of 2048 where the range allows)
+        const int nw = i < 9 ? kNW[i / 3] : 8, mode = i < 9 ? i % 3 : 3;
         if (i == 9 && !(s->wide_ok && j.blk_ngroups == 0 && j.blk_coefB == 0)) {
             if (ms)
                 ms[i] = -1.f;
@@ -319,7 +318,7 @@ hp_status hp_autotune_blocked(const hp_structs *s, const void *d_ws, uint64_t se
         (void)hipEventDestroy(e1);
     if (err != hipSuccess)
         return fail(HP_EDEVICE, std::string("hp_autotune_blocked: ") + hipGetErrorString(err));
-    const int bnw = bi < 9 ? kNW[bi / 3] : 4, bmode = bi < 9 ? bi % 3 : 3;
+    const int bnw = bi < 9 ? kNW[bi / 3] : 8, bmode = bi < 9 ? bi % 3 : 3;
     g_blocked_nw.store(bnw);
     g_blocked_mode.store(bmode);
     if (best_nw)

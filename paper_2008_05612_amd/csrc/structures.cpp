@@ -679,26 +679,26 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
 
     // Wide blocks (pure pair energies), three geometries: plain (the low 10
     // monomers vary), reversal-canonical (the 10 around the middle) and
-    // plain 12 (monomers 0 .. 4 and 6, 8, .., 18; N >= 19), see
+    // plain 11 (monomers 0 .. 4 and 6, 8, .., 16; N >= 17), see
     // hp_internal.h.  Wave w of the workgroup holds the 256 sequences whose
-    // varying monomers above the low 8 are the bits of w (4 waves, or 16 for
-    // plain 12).  Same first-product matrix and key scale as above; the
+    // varying monomers above the low 8 are the bits of w (4 waves, or 8 for
+    // plain 11).  Same first-product matrix and key scale as above; the
     // virtual rows are m = 0 the block term, 1 .. nb the weight of varying
     // monomer m - 1, then the 16 varying pairs (kLow10Pairs, kMid10OddPairs
-    // for odd N canonical, kW12Pairs), then the two index bytes.  Lane l of
+    // for odd N canonical, kW11Pairs), then the two index bytes.  Lane l of
     // tile t of wave w holds block sequence x = 256 w + 32 t + (l & 31) and
     // its byte q the indicator of row m = 8 (q / 4) + 4 (l / 32) + q % 4.
     s->wide_ok = false;
     s->wide_s2.clear();
     const int wodd = N & 1;
     const int whalf = N >= kWideBits ? (N - kWideBits - wodd) / 2 : 0;
-    const int n_geom = N >= kWide12ChunkBits ? 3 : 2;
-    auto wide_nb = [&](int g) { return g == 2 ? kWide12Bits : kWideBits; };
+    const int n_geom = N >= kWide11ChunkBits ? 3 : 2;
+    auto wide_nb = [&](int g) { return g == 2 ? kWide11Bits : kWideBits; };
     auto wide_pos = [&](int g, int x) {
         return g == 0 ? x : g == 1 ? whalf + x + (x >= 5 ? wodd : 0) : (x < 5 ? x : 2 * x - 4);
     };
     auto wide_pair = [&](int g, int p) {
-        const uint64_t w = g == 2 ? (p < 8 ? kW12Pairs0 : kW12Pairs1)
+        const uint64_t w = g == 2 ? (p < 8 ? kW11Pairs0 : kW11Pairs1)
                            : (g == 1 && wodd) ? (p < 8 ? kMid10OddPairs0 : kMid10OddPairs1)
                                               : (p < 8 ? kLow10Pairs0 : kLow10Pairs1);
         return int((w >> (8 * (p & 7))) & 0xffu);
@@ -725,7 +725,7 @@ hp_status build_structures(int X, int Y, int Z, const int32_t table[4], hp_struc
         s->wide_ok = int64_t(s->blk_coef) * maxw <= 128;
     }
     if (s->wide_ok) {
-        const int n_waves = n_geom == 3 ? 4 + 4 + kWide12Waves : 4 + 4;
+        const int n_waves = n_geom == 3 ? 4 + 4 + kWide11Waves : 4 + 4;
         s->wide_s2.assign(size_t(n_waves) * 8 * 64 * 16, 0);
         for (int slot = 0; slot < n_waves; ++slot) {
             const int g = slot < 4 ? 0 : slot < 8 ? 1 : 2;

@@ -7,7 +7,7 @@ import bench
 
 
 def test_summary_file_per_kernel_family():
-    assert bench._summary_name("k_gemm_wide12<5>", "hbm_traffic") == \
+    assert bench._summary_name("k_gemm_wide_w8<5>", "hbm_traffic") == \
         "k_gemm_wide_3x3x3_hbm_traffic.txt"
     assert bench._summary_name("k_gemm_blk<5,4,2>", "issue_counters") == \
         "k_gemm_blk_3x3x3_issue_counters.txt"
@@ -18,7 +18,7 @@ def test_recorded_figures_tied_to_kernel_and_sources():
     assert os.path.exists(path)
     f = bench._summary_fields("k_gemm_wide_3x3x3_hbm_traffic.txt")
     kname = f["kernel"]
-    assert kname in ("k_gemm_wide<5>", "k_gemm_wide12<5>")
+    assert kname in ("k_gemm_wide<5>", "k_gemm_wide_w8<5>")
     sha = f["source_sha"]
     assert bench.recorded_traffic(kname, sha) == float(f["traffic_bytes_per_launch"])
     # another kernel, or another build of the kernel sources: no figure

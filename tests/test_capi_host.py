@@ -156,9 +156,9 @@ def test_argument_errors(lib):
     assert lib.hp_enumerate(heavy.handle, fake_ws, 2, 0, 16, None, None, None, None, None) == -5
     assert lib.hp_enumerate(s.handle, fake_ws, 3, 0, 16, None, None, None, None, None) == -1
     assert lib.hp_blocked_select(3, 0) == -1 and lib.hp_blocked_select(4, 4) == -1
-    assert lib.hp_blocked_select(2, 3) == -1      # wide blocks run 4 or 16 waves per workgroup
-    assert lib.hp_blocked_select(16, 0) == -1 and lib.hp_blocked_select(16, -1) == -1
-    assert lib.hp_blocked_select(16, 3) == 0 and hp.hp_blocked_selected() == (16, 3)
+    assert lib.hp_blocked_select(2, 3) == -1      # wide blocks run 4 or 8 waves per workgroup
+    assert lib.hp_blocked_select(16, 3) == -1 and lib.hp_blocked_select(16, -1) == -1
+    assert lib.hp_blocked_select(8, 3) == 0 and hp.hp_blocked_selected() == (8, 3)
     assert lib.hp_blocked_select(4, -1) == 0
     assert lib.hp_autotune_blocked(tiny.handle, fake_ws, 0, 16, 1, None, None, None, None) == -5
     assert lib.hp_autotune_blocked(s.handle, fake_ws, 0, (1 << 16) + 1, 1, None, None, None,
@@ -277,23 +277,27 @@ def test_mid10_odd_pair_list_is_every_odd_pair():
     assert sorted(got) == want and len(set(got)) == 16
 
 
-def test_wide12_pair_list_is_every_odd_pair():
-    # 4096-sequence wide blocks: x-indices 0 .. 4 at monomers 0 .. 4, 5 .. 11
-    # at the even monomers 6 .. 18; a chunk of 2^19 sequences holds 128 blocks
+def test_wide11_pair_list_is_every_odd_pair():
+    # 2048-sequence wide blocks: x-indices 0 .. 4 at monomers 0 .. 4, 5 .. 10
+    # at the even monomers 6 .. 16; a chunk of 2^17 sequences holds 64 blocks
     src = open(os.path.join(ROOT, "paper_2008_05612_amd", "csrc", "hp_internal.h")).read()
-    words = [int(re.search(r"kW12Pairs%d = (0x[0-9A-Fa-f]+)ull" % i, src).group(1), 16)
+    words = [int(re.search(r"kW11Pairs%d = (0x[0-9A-Fa-f]+)ull" % i, src).group(1), 16)
              for i in (0, 1)]
     got = [((words[p // 8] >> (8 * (p % 8))) & 15, ((words[p // 8] >> (8 * (p % 8))) >> 4) & 15)
            for p in range(16)]
-    pos = [x if x < 5 else 2 * x - 4 for x in range(12)]
-    want = [(a, b) for a in range(12) for b in range(a + 1, 12)
+    pos = [x if x < 5 else 2 * x - 4 for x in range(11)]
+    want = [(a, b) for a in range(11) for b in range(a + 1, 11)
             if pos[b] - pos[a] >= 3 and (pos[b] - pos[a]) % 2]
-    assert sorted(got) == want and len(set(got)) == 16
-    assert 1 + 12 + 16 + 2 <= 32
-    # varying and outer monomers of a chunk partition monomers 0 .. 18
-    outer = [5 + 2 * k for k in range(7)]
-    assert sorted(pos + outer) == list(range(19))
-    assert int(re.search(r"kWide12ChunkBits = (\d+);", src).group(1)) == 19
+    real = [pr for pr in got if (pos[pr[1]] - pos[pr[0]]) % 2]
+    pad = [pr for pr in got if not (pos[pr[1]] - pos[pr[0]]) % 2]
+    assert sorted(real) == want and len(set(real)) == 14
+    # the two padding pairs have equal parity: never in contact, rows stay zero
+    assert len(pad) == 2 and all(a < b for a, b in pad)
+    assert 1 + 11 + 16 + 2 <= 32
+    # varying and outer monomers of a chunk partition monomers 0 .. 16
+    outer = [5 + 2 * k for k in range(6)]
+    assert sorted(pos + outer) == list(range(17))
+    assert int(re.search(r"kWide11ChunkBits = (\d+);", src).group(1)) == 17
 
 
 def test_wide_block_count(lib):

@@ -116,7 +116,7 @@ def test_blocked_pair_table_weight_three(dims, lo, hi):
 
 
 @pytest.mark.parametrize("nw,mode", [(2, 0), (4, 0), (8, 0), (2, 1), (4, 1), (8, 1), (2, 2), (4, 2),
-                                     (8, 2), (4, 3), (16, 3)])
+                                     (8, 2), (4, 3), (8, 3)])
 def test_blocked_every_launch_shape(nw, mode):
     keep = hp.hp_blocked_selected()
     try:
@@ -247,7 +247,7 @@ def test_autotune_blocked_selects_a_shape_and_keeps_results():
         assert (nw, mode) == hp.hp_blocked_selected()
         assert len(ms) == 10 and min(ms) > 0       # wide blocks apply to 5x5
         assert (nw, mode) in [(2, 0), (2, 1), (2, 2), (4, 0), (4, 1), (4, 2), (8, 0), (8, 1),
-                              (8, 2), (4, 3)]
+                              (8, 2), (8, 3)]
         assert ms[9 if mode == 3 else [2, 4, 8].index(nw) * 3 + mode] == min(ms)
         _assert_equal(run((5, 5, 1), BLK, 777, 777 + 5000), _oracle((5, 5, 1), 777, 777 + 5000))
     finally:
@@ -255,8 +255,8 @@ def test_autotune_blocked_selects_a_shape_and_keeps_results():
 
 
 # ---------------------------------------------------------------------------
-# wide blocks (staging mode 3): 1024 sequences per workgroup, first product
-# shared by the waves
+# wide blocks (staging mode 3) on 4 waves: 1024 sequences per workgroup,
+# first product shared by the waves
 # ---------------------------------------------------------------------------
 
 @pytest.fixture()
@@ -314,31 +314,33 @@ def test_wide_full_map_equals_popcount(wide, dims):
 
 
 # ---------------------------------------------------------------------------
-# wide blocks of 4096 sequences (16 waves, selected with nw 16): plain ranges
-# whose ends are multiples of 2^19 on lattices with N >= 19
+# wide blocks of 2048 sequences (8 waves; the default, or nw 8 with mode 3):
+# plain ranges whose ends are multiples of 2^17 on lattices with N >= 17
 # ---------------------------------------------------------------------------
 
-C19 = 1 << 19
+C17 = 1 << 17
 
 
 @pytest.fixture()
-def wide16():
+def wide8():
     keep = hp.hp_blocked_selected()
-    hp.hp_blocked_select(16, 3)
+    hp.hp_blocked_select(8, 3)
     yield
     hp.hp_blocked_select(*keep)
 
 
-@pytest.mark.parametrize("dims,lo,hi", [((5, 5, 1), C19, 2 * C19), ((2, 3, 4), 0, C19)])
-def test_wide12_chunk_matches_oracle(wide16, dims, lo, hi):
-    """One 2^19 chunk (128 blocks of 4096) against the oracle, every sequence."""
+@pytest.mark.parametrize("dims,lo,hi", [((5, 5, 1), C17, 3 * C17), ((2, 3, 4), 0, C17),
+                                        ((4, 5, 1), 5 * C17, 7 * C17)])
+def test_wide8_chunks_match_oracle(wide8, dims, lo, hi):
+    """2^17-sequence chunks (64 blocks of 2048 each) against the oracle, every
+    sequence."""
     _assert_equal(run(dims, BLK, lo, hi), _oracle(dims, lo, hi))
 
 
-@pytest.mark.parametrize("dims,lo,hi", [((2, 3, 4), 3 * C19, 5 * C19),
-                                        ((3, 3, 3), 37 * C19, 39 * C19),
-                                        ((6, 6, 1), (1 << 35) - C19, (1 << 35) + C19)])
-def test_wide12_chunks_equal_popcount(wide16, dims, lo, hi):
+@pytest.mark.parametrize("dims,lo,hi", [((2, 3, 4), 3 * C17, 9 * C17),
+                                        ((3, 3, 3), 37 * C17, 41 * C17),
+                                        ((6, 6, 1), (1 << 35) - C17, (1 << 35) + C17)])
+def test_wide8_chunks_equal_popcount(wide8, dims, lo, hi):
     """Several chunks (6x6: across the middle of the sequence space, K_pad 320)
     equal the popcount form's map, energies and histogram bit for bit, and
     the same range cut one sequence short (blocks of 1024) agrees too."""
@@ -351,9 +353,9 @@ def test_wide12_chunks_equal_popcount(wide16, dims, lo, hi):
     assert np.array_equal(c["out"], a["out"][1:]) and np.array_equal(c["emin"], a["emin"][1:])
 
 
-def test_wide12_gap_threshold(wide16):
+def test_wide8_gap_threshold(wide8):
     import torch
-    dims, lo, hi = (5, 5, 1), 2 * C19, 3 * C19
+    dims, lo, hi = (5, 5, 1), 4 * C17, 6 * C17
     s = hp.Structures(*dims)
     ws = s.workspace()
     st = oracle.structures(*dims)
@@ -368,20 +370,20 @@ def test_wide12_gap_threshold(wide16):
         assert np.array_equal(g.cpu().numpy(), gs.gap), th
 
 
-def test_wide12_full_3x3x3_map_equals_default(wide16):
-    """The full 3x3x3 map with 16-wave blocks of 4096 equals the default
-    shape's map and histogram bit for bit."""
+def test_wide8_full_3x3x3_map_equals_4_waves(wide8):
+    """The full 3x3x3 map with 8-wave blocks of 2048 equals the 4-wave
+    blocks' map and histogram bit for bit."""
     import torch
-    o16, d16, n16 = _full_map_invariants((3, 3, 3), BLK)
-    hp.hp_blocked_select(4, -1)
+    o8, d8, n8 = _full_map_invariants((3, 3, 3), BLK)
+    hp.hp_blocked_select(4, 3)
     o4, d4, n4 = _full_map_invariants((3, 3, 3), BLK)
-    assert torch.equal(o16, o4)
-    assert np.array_equal(d16, d4) and n16 == n4
+    assert torch.equal(o8, o4)
+    assert np.array_equal(d8, d4) and n8 == n4
 
 
 @pytest.mark.parametrize("dims", [(3, 4, 1), (4, 4, 1), (2, 3, 3)])
-def test_wide16_selection_on_canonical_blocks(wide16, dims):
-    """With 16 waves selected, reversal-canonical blocks keep their own
+def test_wide8_selection_on_canonical_blocks(wide8, dims):
+    """With 8 waves selected, reversal-canonical blocks keep their own
     geometry: the symmetric map still equals the oracle's."""
     s = hp.Structures(*dims)
     nb = hp.hp_canonical_block_count(s)

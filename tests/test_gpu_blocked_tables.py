@@ -113,7 +113,7 @@ def test_tables_gap_threshold(dims, lo, hi, thresholds):
 
 
 @pytest.mark.parametrize("nw,mode", [(2, 0), (4, 0), (8, 0), (2, 1), (4, 1), (8, 1), (2, 2), (4, 2),
-                                     (8, 2), (16, 3)])
+                                     (8, 2), (8, 3)])
 def test_tables_every_launch_shape(nw, mode):
     keep = hp.hp_blocked_selected()
     try:
