@@ -294,9 +294,10 @@ hp_status hp_sample(const hp_structs *s, const void *d_ws, int form, uint64_t se
 /*
  * Batched launch: several enumeration jobs, possibly of different lattices
  * and uneven sizes, from one work list of fixed-size items (256 sequences
- * for HP_FORM_GEMM_I8; for HP_FORM_BLOCKED_I8 one wide block of 1024 where
- * wide blocks apply and the selected staging mode is -1 or 3, else 4 blocks
- * of 256).  Jobs are grouped by product depth (hp_info.K_pad; blocked: also
+ * for HP_FORM_GEMM_I8; for HP_FORM_BLOCKED_I8 one wide block where wide
+ * blocks apply and the selected staging mode is -1 or 3 -- of 2048 when the
+ * job's range ends are multiples of 2^17, N >= 17 and 8 waves are allowed
+ * (mode -1, or nw 8), else of 1024 -- otherwise 4 blocks of 256).  Jobs are grouped by product depth (hp_info.K_pad; blocked: also
  * by wide blocks and unary rows) and each group is one kernel launch,
  * compiled for that depth, with one workgroup per item; the groups
  * are enqueued back to back on `stream`.  HP_FORM_POPCOUNT runs the jobs as

@@ -66,11 +66,17 @@ hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, c
         kb_max = std::max(kb_max, int(jobs[i].structs->K_pad / 32));
     }
     // blocked jobs group by depth, by whether they carry unary rows and by
-    // whether they run as wide blocks: key 4 depth + 2 wide + unary
+    // the wide blocks they run as (0 none, 1 of 1024, 2 of 2048): key
+    // 8 depth + 2 wide + unary
+    auto wide_kind = [&](int i) {
+        const hp_job &jb = jobs[i];
+        return blk_batch_wide8(jb.structs, jb.seq_lo, jb.seq_hi) ? 2u
+               : blk_batch_wide(jb.structs)                         ? 1u
+                                                                    : 0u;
+    };
     auto depth = [&](int i) {
         const hp_structs *t = jobs[i].structs;
-        return int(blocked ? 4 * t->blk_KB + (blk_batch_wide(t) ? 2u : 0u) +
-                                 (t->blk_coefB != 0 ? 1u : 0u)
+        return int(blocked ? 8 * t->blk_KB + 2 * wide_kind(i) + (t->blk_coefB != 0 ? 1u : 0u)
                            : t->K_pad / 32);
     };
     // stable insertion sort by depth (batches hold a handful of jobs)
@@ -86,7 +92,9 @@ hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, c
     for (int r = 0; r < njobs; ++r) {
         const hp_job &jb = jobs[order[r]];
         uint64_t items;
-        if (blocked && blk_batch_wide(jb.structs)) {
+        if (blocked && wide_kind(order[r]) == 2) {
+            items = ((jb.seq_hi - jb.seq_lo) >> kWide11ChunkBits) << 6;
+        } else if (blocked && blk_batch_wide(jb.structs)) {
             items = ((jb.seq_hi - 1) >> kWideBits) - (jb.seq_lo >> kWideBits) + 1;
         } else if (blocked) {
             const uint64_t nblk = ((jb.seq_hi - 1) >> kBlkBits) - (jb.seq_lo >> kBlkBits) + 1;
@@ -134,8 +142,8 @@ hipError_t launch_plan(const BatchGroup *groups, int ngroups, int form, void *d_
         if (g.item_hi <= g.item_lo)
             continue;
         hipError_t e = form == HP_FORM_BLOCKED_I8
-                           ? launch_gemm_blk_batch(d_batch_ws, g.kb >> 2, (g.kb & 1) != 0,
-                                                   (g.kb & 2) != 0, g.item_lo, g.item_hi, st)
+                           ? launch_gemm_blk_batch(d_batch_ws, g.kb >> 3, (g.kb & 1) != 0,
+                                                   (g.kb >> 1) & 3, g.item_lo, g.item_hi, st)
                            : launch_gemm_batch(d_batch_ws, g.kb, g.item_lo, g.item_hi, st);
         if (e != hipSuccess)
             return e;

@@ -859,10 +859,43 @@ __global__ __launch_bounds__(256) void k_gemm_wide_batch(BatchHeader *hdr, int i
     wide_body<KB, 0>(j, (j.lo >> kWideBits) + uint64_t(it - start[lo]), vlds, a2s, gbs);
 }
 
+// The same with blocks of 2048 sequences on 8 waves, for jobs whose range
+// ends are multiples of 2^17: item b of a job is its block b of the chunked
+// 2048-sequence geometry.
 template <int KB>
-hipError_t launch_wide_batch(BatchHeader *hdr, int item_lo, unsigned grid, hipStream_t st)
+__global__ __launch_bounds__(512) void k_gemm_wide_batch_w8(BatchHeader *hdr, int item_lo)
 {
-    hipLaunchKernelGGL((k_gemm_wide_batch<KB>), dim3(grid), dim3(256), 0, st, hdr, item_lo);
+    __shared__ v4i vlds[KB * 64];
+    __shared__ v4i a2s[2 * kWide11Waves * 64];
+    __shared__ int2 gbs[kWide11Waves * kBlkTiles * 64];
+    const EnumJob *jobs = reinterpret_cast<const EnumJob *>(hdr + 1);
+    const int njobs = hdr->njobs;
+    const int64_t *start = reinterpret_cast<const int64_t *>(jobs + njobs);
+    const int it = item_lo + int(blockIdx.x);
+    int lo = 0, hi = njobs - 1;   // job with start[job] <= it < start[job+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (start[mid] <= it)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const EnumJob &j = jobs[lo];
+    wide_body<KB, 2>(j, ((j.lo >> kWide11ChunkBits) << 6) + uint64_t(it - start[lo]), vlds, a2s,
+                     gbs);
+}
+
+// wide: 1 blocks of 1024 on 4 waves, 2 blocks of 2048 on 8 waves
+template <int KB>
+hipError_t launch_wide_batch(BatchHeader *hdr, int item_lo, unsigned grid, int wide,
+                             hipStream_t st)
+{
+    if (wide == 2)
+        hipLaunchKernelGGL((k_gemm_wide_batch_w8<KB>), dim3(grid), dim3(512), 0, st, hdr,
+                           item_lo);
+    else
+        hipLaunchKernelGGL((k_gemm_wide_batch<KB>), dim3(grid), dim3(256), 0, st, hdr, item_lo);
     return hipGetLastError();
 }
 
@@ -895,11 +928,11 @@ hipError_t launch_wide(const EnumJob &j, bool waves8, hipStream_t st)
 }
 
 template <int KB>
-hipError_t launch_blk_batch_kb(BatchHeader *hdr, int item_lo, unsigned grid, bool unary, bool wide,
+hipError_t launch_blk_batch_kb(BatchHeader *hdr, int item_lo, unsigned grid, bool unary, int wide,
                                hipStream_t st)
 {
     if (wide)
-        return unary ? hipErrorInvalidValue : launch_wide_batch<KB>(hdr, item_lo, grid, st);
+        return unary ? hipErrorInvalidValue : launch_wide_batch<KB>(hdr, item_lo, grid, wide, st);
     constexpr int MODE = KB <= 6 ? kBlkLdsS2 : kBlkLds;
     if constexpr (KB <= kBlkUnaryMaxKB) {
         if (unary) {
@@ -987,7 +1020,7 @@ hipError_t launch_blk(const EnumJob &j, int nw, int mode, hipStream_t st)
         return launch_blk<KB>(j, nw, mode, st);                                           \
     }                                                                                     \
     hipError_t launch_gemm_blk_batch_kb##KB(BatchHeader *hdr, int item_lo, unsigned grid,  \
-                                            bool unary, bool wide, hipStream_t st)        \
+                                            bool unary, int wide, hipStream_t st)         \
     {                                                                                     \
         return launch_blk_batch_kb<KB>(hdr, item_lo, grid, unary, wide, st);              \
     }                                                                                     \

@@ -8,7 +8,7 @@ namespace hpmap {
 #define HP_BLK_DECLARE(KB)                                                                    \
     hipError_t launch_gemm_blocked_kb##KB(const EnumJob &j, int nw, int mode, hipStream_t st); \
     hipError_t launch_gemm_blk_batch_kb##KB(BatchHeader *hdr, int item_lo, unsigned grid,     \
-                                            bool unary, bool wide, hipStream_t st);           \
+                                            bool unary, int wide, hipStream_t st);            \
     hipError_t launch_gemm_wide_kb##KB(const EnumJob &j, hipStream_t st);
 HP_BLK_DECLARE(1)
 HP_BLK_DECLARE(2)
@@ -27,7 +27,7 @@ HP_BLK_DECLARE(12)
 namespace {
 
 using BlockedLaunch = hipError_t (*)(const EnumJob &, int, int, hipStream_t);
-using BlockedBatchLaunch = hipError_t (*)(BatchHeader *, int, unsigned, bool, bool, hipStream_t);
+using BlockedBatchLaunch = hipError_t (*)(BatchHeader *, int, unsigned, bool, int, hipStream_t);
 
 // Index = product depth / 32 (1 .. kMaxKB).
 const BlockedLaunch kBlocked[] = {
@@ -63,7 +63,15 @@ bool blk_batch_wide(const hp_structs *s)
     return s->wide_ok && (mode < 0 || mode == kBlkStageWide);
 }
 
-hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, bool wide, int item_lo,
+bool blk_batch_wide8(const hp_structs *s, uint64_t lo, uint64_t hi)
+{
+    const uint64_t m = (uint64_t(1) << kWide11ChunkBits) - 1;
+    const int mode = blocked_selected_mode();
+    return blk_batch_wide(s) && (mode < 0 || blocked_selected_nw() == 8) &&
+           s->N >= kWide11ChunkBits && hi > lo && (lo & m) == 0 && (hi & m) == 0;
+}
+
+hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, int wide, int item_lo,
                                  int item_hi, hipStream_t st)
 {
     if (kb < 1 || kb > kDepths)

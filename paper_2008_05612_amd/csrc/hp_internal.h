@@ -144,7 +144,8 @@ EnumJob make_enum_job(const hp_structs *s, const void *d_ws, uint64_t lo, uint64
 // start[njobs + 1] and groups[njobs] are scratch and launch groups supplied
 // by the caller (nothing is allocated).
 struct BatchGroup {
-    int kb, item_lo, item_hi;   // product depth (blocked: 4 depth + 2 wide + unary), its items
+    int kb, item_lo, item_hi;   // product depth (blocked: 8 depth + 2 wide + unary, wide 0 none,
+                                // 1 blocks of 1024, 2 blocks of 2048), its items
 };
 hp_status plan_batch(const hp_job *jobs, int njobs, int form, size_t ws_bytes, char *host,
                      int *order, int64_t *start, BatchGroup *groups, int *ngroups);

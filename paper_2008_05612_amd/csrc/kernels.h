@@ -98,11 +98,14 @@ hipError_t launch_gemm_wide_canonical(const EnumJob &j, hipStream_t st);
 // the first product shared by the waves (pure pair energies, plain ranges).
 enum BlkStage { kBlkStageLds = 0, kBlkStagePipe = 1, kBlkStageS2Lds = 2, kBlkStageWide = 3 };
 // Batched launch of the blocked form (plain jobs), same work-list layout:
-// items of blk_batch_seqs_per_item() sequences, one wide block (wide jobs:
-// blk_batch_wide) or 4 blocks of 256, one workgroup per item.
+// items of blk_batch_seqs_per_item() sequences, one wide block of 1024 (wide
+// jobs: blk_batch_wide) or 4 blocks of 256, or one wide block of 2048 (jobs
+// whose range ends are multiples of 2^17: blk_batch_wide8), one workgroup per
+// item; wide = 0, 1 (blocks of 1024) or 2 (blocks of 2048).
 uint64_t blk_batch_seqs_per_item();
 bool blk_batch_wide(const hp_structs *s);
-hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, bool wide, int item_lo,
+bool blk_batch_wide8(const hp_structs *s, uint64_t lo, uint64_t hi);
+hipError_t launch_gemm_blk_batch(void *d_batch_ws, int kb, bool unary, int wide, int item_lo,
                                  int item_hi, hipStream_t st);
 // Process-wide launch shape of the blocked form (runtime.cpp).
 int blocked_selected_nw();
