@@ -18,8 +18,11 @@ from tests import _golden333 as g333
 from tests.conftest import gpu_available
 
 pytestmark = pytest.mark.gpu
-# form and, for the blocked form, its launch shape (waves, staging mode)
+# form and, for the blocked form, its launch shape (waves, staging mode):
+# per-wave blocks, wide blocks of 1024 on 4 waves, of 2048 on 8 waves, and the
+# default shape (the benchmark's)
 FORMS = {"blocked_i8": (hp.FORM_BLOCKED_I8, (4, 2)), "blocked_i8_wide": (hp.FORM_BLOCKED_I8, (4, 3)),
+         "blocked_i8_wide8": (hp.FORM_BLOCKED_I8, (8, 3)), "blocked_i8_default": (hp.FORM_BLOCKED_I8, (4, -1)),
          "gemm_i8": (hp.FORM_GEMM_I8, None), "popcount": (hp.FORM_POPCOUNT, None)}
 
 
@@ -76,7 +79,7 @@ def test_three_forms_agree(full_maps):
     s, res, canon = full_maps
     ref = res["blocked_i8"]
     assert not bool((ref[0] == -2).any())
-    for name in ("blocked_i8_wide", "gemm_i8", "popcount"):
+    for name in ("blocked_i8_wide", "blocked_i8_wide8", "blocked_i8_default", "gemm_i8", "popcount"):
         assert torch.equal(res[name][0], ref[0]), name
         assert np.array_equal(res[name][1], ref[1]), name
         assert res[name][2] == ref[2], name
