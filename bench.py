@@ -223,7 +223,8 @@ def main():
                         "counts + union-find",
             "lattice": "3x3x3", "N": N, "sequences": total, "n_conf": n_conf,
             "n_class": s.n_class, "K": s.K, "K_pad": s.K_pad, "nbp": s.nbp,
-            "form": "blocked_i8", "waves_per_workgroup": nw, "staging_mode": blk_mode,
+            "form": "blocked_i8", "waves_per_workgroup": 8 if wide8 else nw,
+            "staging_mode": blk_mode, "block_sequences": block_seqs,
         },
         "roofline": {
             "bound": "mfma",
