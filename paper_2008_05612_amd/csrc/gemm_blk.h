@@ -298,8 +298,13 @@ __device__ __forceinline__ void stage_two(const v4i &a2, const v4i (&sf)[S2_LDS 
 // two changes that free registers for a third accumulator (four waves per
 // SIMD still fit): the running top-2 of each lane lives in LDS (g[t * 64],
 // read and written only by the rare key update), and the product of
-// sequence tile t + 2 is issued before tile t's test, so each test reads a
-// product issued a full test earlier.
+// sequence tile t + 2 is issued right after tile t's test, so each test reads
+// a product issued a full test earlier.  Issuing that product after the test
+// rather than before or inside it measured fastest (full 3x3x3 map, 8 waves:
+// 310 ms against 314 ms where the compiler placed it and 318 ms before the
+// test): a wave that reaches an MFMA while the matrix pipe still runs another
+// wave's product waits there, and after its nine test instructions the pipe
+// is more often free.
 __device__ __forceinline__ void stage_two_wide(const v4i &a2, const v4i (&sf)[kBlkTiles], int2 *g,
                                                int (&thr)[kBlkTiles], int conf_base,
                                                int win_shift)
@@ -313,7 +318,13 @@ __device__ __forceinline__ void stage_two_wide(const v4i &a2, const v4i (&sf)[kB
         if (t + 2 < kBlkTiles)
             acc[(t + 2) % 3] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sf[t + 2], zero, 0, 0, 0);
         const v16i &a = acc[t % 3];
-        if (__builtin_expect(__any(max16(a) >= thr[t]), 0)) {
+        const bool hit = __any(max16(a) >= thr[t]);
+        if (t + 2 < kBlkTiles) {
+            // the test's 9 vector instructions (8 v_max3, 1 compare), then the MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 9, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+        if (__builtin_expect(hit, 0)) {
             int b = 0, sc = 0;
 #pragma unroll
             for (int r = 0; r < 16; r += 2)
@@ -678,9 +689,9 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
                            : G == 2 ? wide11_outer(blk)
                                     : blk << kWideBits;
     // Contact tiles of the first product are loaded one group ahead into
-    // registers for shallow products; deep ones (K_pad > 192, or > 160 with
-    // 8 waves) load right before use, which keeps four waves per SIMD.
-    constexpr bool kPrefetch = KB <= (NW == 4 ? 6 : 5);
+    // registers for shallow products; deep ones (K_pad > 160) load right
+    // before use, which keeps four waves per SIMD.
+    constexpr bool kPrefetch = KB <= 5;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 31;
@@ -746,19 +757,38 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
     __syncthreads();
     int conf_base = 0;
     int wnext = win_tiles;   // first tile of the next key window
+    // The packed first product of the next tile is read from LDS one tile
+    // ahead, so no tile starts by waiting for it.  With 8 waves the group's
+    // barrier sits before its last tile: by then every wave has read all of
+    // this group's buffer and written its first product of the next group,
+    // so the next group's first tile can be read ahead as well.  (With 4 waves
+    // that costs registers beyond four waves per SIMD; the barrier stays at
+    // the group's end and each group's first tile is read at its start.)
+    constexpr bool kEarlyBarrier = NW == 8;
+    v4i a2n = a2s[lane];
     for (int g = 0; g * NW < n_tiles; ++g) {
         const int buf = g & 1;
         const int nt = (g + 1) * NW + wave;   // this wave's tile of the next group
+        if constexpr (!kEarlyBarrier)
+            a2n = a2s[(buf * NW) * 64 + lane];
 #pragma unroll
         for (int tt = 0; tt < NW; ++tt) {
             const int tile = g * NW + tt;
+            const v4i a2 = a2n;
+            if (tt + 1 < NW) {
+                a2n = a2s[(buf * NW + tt + 1) * 64 + lane];
+            } else if constexpr (kEarlyBarrier) {
+                // the next group's first products are visible, and this
+                // group's buffer is free for the group after it
+                __syncthreads();
+                a2n = a2s[((buf ^ 1) * NW) * 64 + lane];
+            }
             if (tile < n_tiles) {
                 if (tile == wnext) {
                     conf_base += win_tiles * kTileConf;
                     wnext += win_tiles;
                 }
-                stage_two_wide(a2s[(buf * NW + tt) * 64 + lane], sf, top2, thr, conf_base,
-                               win_shift);
+                stage_two_wide(a2, sf, top2, thr, conf_base, win_shift);
             }
             if (tt == 0 && nt < n_tiles) {
                 if (!kPrefetch)
@@ -768,9 +798,8 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
                     load_c1(nt + NW, c1);
             }
         }
-        // the next group's first products are visible, and this group's
-        // buffer is free for the group after it
-        __syncthreads();
+        if constexpr (!kEarlyBarrier)
+            __syncthreads();   // as above, at the group's end
     }
 
     int gb[kBlkTiles], gs[kBlkTiles];
