@@ -330,10 +330,13 @@ def wide8():
 
 
 @pytest.mark.parametrize("dims,lo,hi", [((5, 5, 1), C17, 3 * C17), ((2, 3, 4), 0, C17),
-                                        ((4, 5, 1), 5 * C17, 7 * C17)])
+                                        ((4, 5, 1), 5 * C17, 7 * C17),
+                                        ((2, 9, 1), 0, 2 * C17), ((3, 6, 1), 0, 2 * C17)])
 def test_wide8_chunks_match_oracle(wide8, dims, lo, hi):
     """2^17-sequence chunks (64 blocks of 2048 each) against the oracle, every
-    sequence."""
+    sequence; 2x9 (2 conformation tiles) and 3x6 (6) have fewer tiles than a
+    workgroup has waves, so only a partial group runs and some waves compute
+    no first product (whole maps, N = 18)."""
     _assert_equal(run(dims, BLK, lo, hi), _oracle(dims, lo, hi))
 
 
