@@ -762,8 +762,10 @@ __device__ __forceinline__ void wide_body(const EnumJob &j, uint64_t blk, v4i *v
     // barrier sits before its last tile: by then every wave has read all of
     // this group's buffer and written its first product of the next group,
     // so the next group's first tile can be read ahead as well.  (With 4 waves
-    // that costs registers beyond four waves per SIMD; the barrier stays at
-    // the group's end and each group's first tile is read at its start.)
+    // that needs registers beyond four waves per SIMD where the contact tiles
+    // are prefetched, and measured slower where they are not; there the
+    // barrier stays at the group's end and each group's first tile is read at
+    // its start.)
     constexpr bool kEarlyBarrier = NW == 8;
     v4i a2n = a2s[lane];
     for (int g = 0; g * NW < n_tiles; ++g) {
