@@ -27,3 +27,15 @@ def test_recorded_figures_tied_to_kernel_and_sources():
     assert bench.recorded_issue(kname, "0" * 16) == {"blocked_issue_counters": None}
     got = bench.recorded_issue(kname, sha)["blocked_issue_counters"]
     assert got is not None and got["mfma_per_wave_tile"] > 0
+
+
+def test_committed_summaries_match_the_kernel_sources():
+    """Every committed wide-kernel summary names the build it was taken on;
+    they were taken together, on the current kernel sources."""
+    names = ["k_gemm_wide_3x3x3_hbm_traffic.txt", "k_gemm_wide_3x3x3_issue_counters.txt",
+             "k_gemm_wide_3x3x3_full_map_kernel_trace.txt",
+             "k_gemm_wide_6x6_full_map_kernel_trace.txt"]
+    shas = {bench._summary_fields(n)["source_sha"] for n in names}
+    assert shas == {bench.kernel_source_hash()}
+    kernels = {bench._summary_fields(n)["kernel"] for n in names[:3]}
+    assert kernels == {"k_gemm_wide_w8<5>"}
